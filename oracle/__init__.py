@@ -1,0 +1,25 @@
+"""Plain FP64 CPU oracle for the hierarchical-simulation CVA path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package imports, calls or links
+this package; only the tests, the smoke check and the benchmark's CPU-baseline leg
+do.  It shares no code with the HIP library: the two sides meet only through the
+seeded input arrays of the ``workloads`` module.
+
+Each function follows the paper's definition of the quantity it computes, in the
+paper's order, with NumPy FP64 arithmetic and no blocking or fusion beyond what
+that definition states.  Where the paper is silent or garbled the docstring names
+the reading taken.
+
+Parity status of the functions (what pins each one, besides the GPU path):
+  philox4x32_10          published known-answer vectors (tests/golden/philox_kat.txt)
+  uniforms / normals     exact grid property, moments, KS against N(0,1)
+  simulate_outer         Vasicek zero-coupon closed form, OU moments, FX martingale
+  zc / swap_price        closed form at t=0 (par swap has zero value), martingale
+  default dates          CIR survival closed form, literal rule on hand cases
+  pathwise loss / T      exact conditional mean/variance, unbiasedness vs n_b=1,
+                         brute-force enumeration on tiny inputs
+  regression (BaseAlg)   least-squares refit == numpy lstsq; h=0 fit == lstsq;
+                         one Adam step == hand-derived update
+  sensitivities (FD)     convergence in h; analytic derivative of a closed form
+"""
+from . import philox, closed_forms, model, inner, pipeline, regression, sensitivities  # noqa: F401

@@ -1,0 +1,99 @@
+"""Inner (oversimulated) default draws, pathwise CVA loss and targets (FP64 oracle).
+
+Default rule (Appendix B, e:tau): counterparty c has defaulted by t iff
+int_0^t gamma^c >= eps^c with eps^c standard exponential; defaults are checked at
+pricing dates only (Remark rem:finecoarse), so the default date index is
+j* = min{ j >= 1 : Lambda^c_j >= eps^c }  (none if the set is empty), with
+eps = -log(u) for the inner uniform u.
+
+Pathwise loss (Section 4.2, eq:CVA_portfolio), read with the sum over j = i..n-1
+(the horizon is the last pricing date) and with the loss-given-default factor:
+    xi_i = sum_c sum_{j=i}^{n-1} (beta_{j+1} / beta_i) LGD_c (MtM^c_{j+1})^+ 1{j < tau_c <= j+1}.
+It is computed by the backward recursion
+    xi_n = 0,  xi_i = (beta_{i+1}/beta_i) (xi_{i+1} + sum_c LGD_c (MtM^c_{i+1})^+ 1{j*_c = i+1}).
+
+Hierarchical simulation (Section 3.2): each outer path k carries n_b conditionally
+independent inner draws l.  The target regressed at date i is the inner average
+    T^k_i = (1/n_b) sum_l xi^{k,l}_i,
+which is an unbiased estimate of E[xi_i | outer path k]; CVA_0 = mean_k T^k_0.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import philox
+
+
+def default_dates(Lam: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """j*[P, n_b, C] from Lambda[n+1, P, C] and uniforms u[P, n_b, C]; n+1 means no default."""
+    n = Lam.shape[0] - 1
+    eps = -np.log(u)
+    jstar = np.full(u.shape, n + 1, dtype=np.int64)
+    for j in range(n, 0, -1):                       # smallest j wins
+        hit = Lam[j][:, None, :] >= eps
+        jstar = np.where(hit, j, jstar)
+    return jstar
+
+
+def pathwise_loss(I: np.ndarray, mtm_c: np.ndarray, lgd: np.ndarray,
+                  jstar: np.ndarray) -> np.ndarray:
+    """xi[n+1, P, n_b] by the backward recursion above."""
+    n = I.shape[0] - 1
+    P, n_b, _ = jstar.shape
+    beta = np.exp(-I)
+    xi = np.zeros((n + 1, P, n_b))
+    for i in range(n - 1, -1, -1):
+        loss_next = np.zeros((P, n_b))
+        pos = np.maximum(mtm_c[i + 1], 0.0)            # [P, C]
+        for c in range(jstar.shape[2]):
+            loss_next += lgd[c] * pos[:, c][:, None] * (jstar[:, :, c] == i + 1)
+        xi[i] = (beta[i + 1] / beta[i])[:, None] * (xi[i + 1] + loss_next)
+    return xi
+
+
+def targets(xi: np.ndarray) -> np.ndarray:
+    """T[n+1, P] = inner average of the pathwise loss."""
+    return xi.mean(axis=2)
+
+
+def default_counts(jstar: np.ndarray, n: int) -> np.ndarray:
+    """cnt[n+1, C, P]: number of inner draws of each path defaulting at date j."""
+    P, _, C = jstar.shape
+    cnt = np.zeros((n + 1, C, P), dtype=np.int64)
+    for j in range(1, n + 1):
+        cnt[j] = (jstar == j).sum(axis=1).T
+    return cnt
+
+
+def conditional_moments(I: np.ndarray, Lam: np.ndarray, mtm_c: np.ndarray, lgd: np.ndarray):
+    """Exact mean and variance of xi_i given the outer path, for one inner draw.
+
+    Given the outer path, the eps^c are independent Exp(1), so
+    P(j*_c = j) = exp(-Lambda^c_{j-1}) - exp(-Lambda^c_j), and counterparties are
+    independent: mu_i = sum_c sum_{j>i} a^c_{ij} p^c_j,
+    var_i = sum_c [ sum_{j>i} (a^c_{ij})^2 p^c_j - (sum_{j>i} a^c_{ij} p^c_j)^2 ],
+    with a^c_{ij} = LGD_c (beta_j / beta_i) (MtM^c_j)^+.
+    This is also the smoothed (conditional) CVA estimator differentiated by the
+    sensitivities.
+    """
+    n = I.shape[0] - 1
+    beta = np.exp(-I)
+    surv = np.exp(-Lam)                                 # [n+1, P, C]
+    p = np.zeros_like(surv)
+    p[1:] = surv[:-1] - surv[1:]
+    D = lgd[None, None, :] * beta[:, :, None] * np.maximum(mtm_c, 0.0)
+    mu = np.zeros((n + 1, I.shape[1]))
+    var = np.zeros_like(mu)
+    for i in range(n + 1):
+        a = D[i + 1:] / beta[i][None, :, None]         # [n-i, P, C]
+        pj = p[i + 1:]
+        m1 = (a * pj).sum(axis=0)                      # [P, C]
+        m2 = (a * a * pj).sum(axis=0)
+        mu[i] = m1.sum(axis=1)
+        var[i] = (m2 - m1 * m1).sum(axis=1)
+    return mu, var
+
+
+def inner_draws(w, paths, n_b=None) -> np.ndarray:
+    n_b = w.n_b if n_b is None else n_b
+    return philox.inner_uniforms(w.seed, paths, n_b, w.market.n_cpty)
