@@ -1,0 +1,206 @@
+/*
+ * hsim.h -- C ABI of the hierarchical-simulation CVA library (libhsim.so, gfx950).
+ *
+ * The library computes the data-parallel path of the hierarchical ("oversimulated")
+ * CVA scheme of Abbas-Turki, Crepey & Saadeddine, "Pathwise CVA regressions with
+ * oversimulated defaults":
+ *   - M outer paths of the market factors (Vasicek short rates, log-normal FX rates,
+ *     CIR default intensities; Appendix B, equations e:sde1 and e:sde2) are stepped
+ *     by Euler on a fine grid (Section 4.1, remark rem:finecoarse);
+ *   - every swap is priced at every pricing date with the three-case formula of
+ *     Appendix B, and the exposures D^c_j = LGD_c beta_j (MtM^c_j)^+ are formed;
+ *   - each outer path carries n_b inner default draws (Section 3.2), with the default
+ *     rule of equation e:tau checked at pricing dates;
+ *   - the pathwise CVA loss of eq:CVA_portfolio is averaged over the inner draws
+ *     into the regression targets T_i, and CVA_0 = mean_k T^k_0;
+ *   - the targets are regressed onto the market state by NN^+ networks (e:nnp),
+ *     trained by BaseAlg (Algorithm 1) and Backward learning (Algorithm 2);
+ *   - the sensitivities of CVA_0 to the model parameters are computed by an adjoint
+ *     sweep of the smoothed (conditional) estimator.
+ *
+ * Conventions
+ *   - Every entry point returns an int status: HSIM_OK (0) or a negative error code.
+ *     A message for the last error of the calling thread is in hsim_last_error().
+ *     No C++ exception crosses the ABI.
+ *   - Pointers named *_dev are device memory owned by the caller (for instance torch
+ *     tensors); the library never frees or keeps them.  Host structs and host arrays
+ *     are read only during the call.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = default
+ *     stream) and is asynchronous unless stated otherwise.
+ *   - Results depend only on the inputs, the seed and global path/draw indices: never
+ *     on grid or block sizes, nor on how a path range is split over calls.
+ *   - Arrays are dense and row-major in the index order written, e.g. [n+1][C][M]
+ *     means element (j, c, k) at offset (j*C + c)*M + k.
+ *   - Arguments are validated before any launch: a null pointer, a non-positive size,
+ *     a correlation matrix that is not positive definite, a reset period that is not a
+ *     whole number of pricing steps, sizes beyond the stated limits, or a workspace
+ *     that is too small return an error and launch nothing.
+ */
+#ifndef HSIM_H
+#define HSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSIM_ABI_VERSION 1
+
+enum hsim_status {
+  HSIM_OK = 0,
+  HSIM_EINVAL = -1,       /* bad argument */
+  HSIM_ERANGE = -2,       /* a size beyond the supported limits */
+  HSIM_ENOWS = -3,        /* workspace too small */
+  HSIM_EDEVICE = -4,      /* a HIP runtime call failed */
+  HSIM_EUNSUPPORTED = -5  /* a shape the library was not built for */
+};
+
+/* Arithmetic of the simulation.  HSIM_FP64: all state and prices in FP64.  HSIM_FP32:
+ * state, normals and prices in FP32; the integrals int r^0 and int gamma^c (hence
+ * beta and Lambda) are always accumulated in FP64. */
+enum hsim_precision { HSIM_FP64 = 0, HSIM_FP32 = 1 };
+
+/* Regression inputs emitted per date.  FACTORS: r^0..r^{n_e-1}, log chi^1..log chi^{n_e-1},
+ * gamma^1..gamma^C (the diffusive factors of Section 4.3).  FACTORS_PLUS adds
+ * I_i = -log beta_i and sum_c Lambda^c_i. */
+enum hsim_features { HSIM_FEAT_FACTORS = 0, HSIM_FEAT_FACTORS_PLUS = 1 };
+
+/* Limits of this build. */
+#define HSIM_MAX_CCY 16
+#define HSIM_MAX_CPTY 16
+#define HSIM_MAX_DATES 512
+#define HSIM_MAX_PERIODS 64
+
+/* Model parameters (Appendix B).  Host pointers.  Brownian ordering of `corr`
+ * (dimension d_W = 2 n_ccy - 1, row-major, symmetric positive definite, unit
+ * diagonal): index e < n_ccy drives r^e, index n_ccy + e - 1 drives log chi^e for
+ * 1 <= e < n_ccy.  The correlation rho^e of (r^e, log chi^e) enters the drift of r^e
+ * under the domestic measure as -rho^e sigma_r^e sigma_fx^e.  CIR drivers are
+ * independent of the market block and of each other. */
+typedef struct {
+  int32_t n_ccy;              /* 1 <= n_ccy <= HSIM_MAX_CCY; currency 0 is the reference */
+  int32_t n_cpty;             /* 1 <= n_cpty <= HSIM_MAX_CPTY */
+  const double* a;            /* [n_ccy] Vasicek speed (> 0) */
+  const double* b;            /* [n_ccy] Vasicek level under Q^e */
+  const double* sigma_r;      /* [n_ccy] Vasicek volatility (>= 0) */
+  const double* r0;           /* [n_ccy] initial short rates */
+  const double* sigma_fx;     /* [n_ccy-1] FX log-volatility (>= 0); may be NULL if n_ccy = 1 */
+  const double* fx0;          /* [n_ccy-1] initial FX rates (> 0); may be NULL if n_ccy = 1 */
+  const double* corr;         /* [(2 n_ccy - 1)^2] */
+  const double* kappa;        /* [n_cpty] CIR speed */
+  const double* theta;        /* [n_cpty] CIR level */
+  const double* nu;           /* [n_cpty] CIR volatility (>= 0) */
+  const double* lambda0;      /* [n_cpty] initial intensity (>= 0) */
+  const double* lgd;          /* [n_cpty] loss given default */
+} hsim_market;
+
+/* Swap book (Appendix B): spot-starting swaps, resets every `delta` years, paying fixed
+ * delta*fixed_rate and receiving floating 1/ZC_{t-}(t) - 1 at every reset date but 0.
+ * payer = +1: the bank pays fixed; payer = -1: the bank receives fixed.  Notionals are
+ * in the swap's currency.  Host pointers. */
+typedef struct {
+  int32_t n_swaps;            /* >= 1 */
+  const int32_t* ccy;         /* [n_swaps] in [0, n_ccy) */
+  const int32_t* cpty;        /* [n_swaps] in [0, n_cpty) */
+  const int32_t* periods;     /* [n_swaps] maturity in reset periods, 1..HSIM_MAX_PERIODS */
+  const double* notional;     /* [n_swaps] */
+  const double* fixed_rate;   /* [n_swaps] swap rate Sigma */
+  const int32_t* payer;       /* [n_swaps] +1 or -1 */
+  double delta;               /* reset period in years (> 0) */
+} hsim_portfolio;
+
+/* Time grid: n_dates pricing dates t_i = i*horizon/n_dates, n_sub Euler sub-steps each.
+ * delta*n_dates/horizon must be a whole number q (pricing steps per reset period), and
+ * every maturity must lie within the horizon. */
+typedef struct {
+  double horizon;
+  int32_t n_dates;            /* 1..HSIM_MAX_DATES */
+  int32_t n_sub;              /* >= 1 */
+} hsim_grid;
+
+int hsim_abi_version(void);
+const char* hsim_last_error(void);
+
+/* Number of regression inputs per date for a feature mode. */
+int hsim_n_features(const hsim_market* market, int feature_mode);
+
+/* Time-0 par rates of the swaps (the fixed rate that makes the t = 0 case of the
+ * Appendix B swap price vanish), in host memory: par_out[n_swaps].  Synchronous. */
+int hsim_par_rates(const hsim_market* market, const hsim_portfolio* book, double* par_out);
+
+/* Test hook: the raw Philox4x32-10 words of counters (k, c1, c2, c3) for
+ * k = k_begin .. k_begin+count-1, with key (seed mod 2^32, seed >> 32):
+ * out_dev[4*(k-k_begin) + w] = word w.  out_dev holds 4*count uint32. */
+int hsim_philox_fill(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t k_begin,
+                     int64_t count, uint32_t* out_dev, void* stream);
+
+/* Test hook: the standard normals that outer path k uses at global sub-step s,
+ * out_dev[(k - path_begin)*n_z + f] for f < n_z, in the given precision (float or
+ * double elements). */
+int hsim_normals_fill(uint64_t seed, int64_t path_begin, int64_t count, int32_t s, int32_t n_z,
+                      int precision, void* out_dev, void* stream);
+
+/* Outer simulation and pricing (Appendix B; Section 4.1 rem:finecoarse; Section 4.2).
+ * Simulates outer paths k = path_begin .. path_begin+M-1 and writes, at every pricing
+ * date j = 0..n (n = grid->n_dates):
+ *   features_dev [n+1][d][M]   regression inputs (float if FP32, double if FP64); may be NULL
+ *   I_dev        [n+1][M]      int_0^{t_j} r^0 (double), beta_j = exp(-I_j); must not be NULL
+ *   Lambda_dev   [n+1][C][M]   int_0^{t_j} gamma^{c,+} (double); must not be NULL
+ *   D_dev        [n+1][C][M]   LGD_c beta_j (MtM^c_j)^+ (float if FP32, double if FP64); must not be NULL
+ *   MtM_dev      [n+1][C][M]   MtM^c_j in the reference currency (same type); may be NULL
+ * No workspace is needed. */
+int hsim_outer_paths(const hsim_market* market, const hsim_portfolio* book, const hsim_grid* grid,
+                     uint64_t seed, int64_t path_begin, int64_t M, int precision, int feature_mode,
+                     void* features_dev, double* I_dev, double* Lambda_dev, void* D_dev,
+                     void* MtM_dev, void* stream);
+
+/* Inner default draws (Section 3.2; Appendix B e:tau).  For every outer path k of the
+ * range and counterparty c, draws l = 0..n_b(k)-1 use the Philox word (k, l>>2, c, 1)
+ * [l&3] -> u = (2 floor(word/2^9) + 1) 2^-24, and default at
+ *   j* = min{ j >= 1 : Lambda^c_j >= -log u }   (no default if none).
+ * counts_dev [n+1][C][M] (int32) receives the number of draws defaulting at each date.
+ * n_b(k) = n_b when n_b_per_block is NULL; otherwise path k uses
+ * n_b_per_block[(k - path_begin) / block_paths] (host array of ceil(M/block_paths)
+ * entries, block_paths a positive multiple of 64).  1 <= n_b(k) <= 2^24.
+ * Needs hsim_workspace_bytes(HSIM_OP_INNER, ...) bytes of device workspace. */
+int hsim_inner_defaults(const hsim_grid* grid, int32_t n_cpty, uint64_t seed, int64_t path_begin,
+                        int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
+                        const double* Lambda_dev, int32_t* counts_dev, void* workspace_dev,
+                        size_t ws_bytes, void* stream);
+
+/* Targets and CVA_0 (Section 4.2 eq:CVA_portfolio; Section 3.2): with the default counts
+ * of hsim_inner_defaults,
+ *   T_i = exp(I_i) / n_b(k) * sum_{j=i+1}^{n} sum_c D^c_j counts^c_j,   T_n = 0,
+ * which is the inner average of the pathwise loss xi_i.  target_dev [n+1][M] (float if
+ * FP32, double if FP64).  cva0_dev (one double, device) receives mean_k T^k_0 over the
+ * range, reduced in a fixed order.  n_b / n_b_per_block / block_paths as above.
+ * Needs hsim_workspace_bytes(HSIM_OP_TARGETS, ...) bytes of device workspace. */
+int hsim_targets_cva(const hsim_grid* grid, int32_t n_cpty, int64_t M, int32_t n_b,
+                     const int32_t* n_b_per_block, int32_t block_paths, int precision,
+                     const double* I_dev, const void* D_dev, const int32_t* counts_dev,
+                     void* target_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,
+                     void* stream);
+
+/* The three stages above in one call: features_dev [n+1][d][M] (may be NULL),
+ * target_dev [n+1][M], cva0_dev (one double).  The intermediate I, Lambda, D and counts
+ * live in the workspace: hsim_workspace_bytes(HSIM_OP_FUSED, ...). */
+int hsim_inner_defaults_cva(const hsim_market* market, const hsim_portfolio* book,
+                            const hsim_grid* grid, uint64_t seed, int64_t path_begin, int64_t M,
+                            int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
+                            int precision, int feature_mode, void* features_dev,
+                            void* target_dev, double* cva0_dev, void* workspace_dev,
+                            size_t ws_bytes, void* stream);
+
+enum hsim_op { HSIM_OP_INNER = 1, HSIM_OP_TARGETS = 2, HSIM_OP_FUSED = 3, HSIM_OP_ADJOINT = 4 };
+
+/* Device workspace (bytes) an operation needs for M paths and the given market/grid. */
+size_t hsim_workspace_bytes(int op, const hsim_market* market, const hsim_grid* grid,
+                            int64_t M, int precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSIM_H */

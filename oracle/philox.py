@@ -7,9 +7,11 @@ Weyl-sequence key schedule.  R = 10 here.
 
 Counter layout (global indices only, never launch geometry):
   outer normals:  (k, s, f >> 2, 0)  path k, global sub-step s, normal index f
-  inner defaults: (k, q >> 2, 0, 1)  q = l * C + c, draw l, counterparty c
+  inner defaults: (k, l >> 2, c, 1)  draw l, counterparty c
   network init:   (layer, idx >> 2, date, 2)
-Key = (seed mod 2^32, seed >> 32).  The word used is ``q & 3`` (``f & 3``).
+Key = (seed mod 2^32, seed >> 32).  The word used is ``l & 3`` (``f & 3``).  Keeping
+the draw index l in the first counter word makes the first n_b' draws of every
+(path, counterparty) a prefix of the first n_b draws, for any n_b >= n_b'.
 
 The paper does not specify a generator; these are the readings documented for
 this build.
@@ -96,14 +98,14 @@ def outer_normals(seed: int, paths: np.ndarray, s: int, n_z: int) -> np.ndarray:
 def inner_uniforms(seed: int, paths: np.ndarray, n_b: int, n_c: int) -> np.ndarray:
     """Uniforms u[path, l, c] for the inner default draws (draw l, counterparty c)."""
     paths = np.asarray(paths, dtype=np.uint64)
-    nq = n_b * n_c
-    n_calls = (nq + 3) // 4
-    out = np.empty((paths.shape[0], 4 * n_calls))
-    for g in range(n_calls):
-        ws = words(seed, paths, g, 0, TAG_INNER)
-        for j in range(4):
-            out[:, 4 * g + j] = uniform(ws[j])
-    return out[:, :nq].reshape(paths.shape[0], n_b, n_c)
+    n_calls = (n_b + 3) // 4
+    out = np.empty((paths.shape[0], 4 * n_calls, n_c))
+    for c in range(n_c):
+        for g in range(n_calls):
+            ws = words(seed, paths, g, c, TAG_INNER)
+            for j in range(4):
+                out[:, 4 * g + j, c] = uniform(ws[j])
+    return out[:, :n_b, :]
 
 
 def raw_words(seed: int, c1: int, c2: int, c3: int, k_begin: int, count: int) -> np.ndarray:

@@ -56,6 +56,6 @@ def simulate(w, path_begin: int = 0, count: int | None = None, n_b: int | None =
     out = {}
     for k, v in res.items():
         if v:
-            out[k] = np.concatenate(v, axis=-1)
+            out[k] = np.ascontiguousarray(np.concatenate(v, axis=-1))
     out["cva0"] = float(out["T"][0].mean())
     return out

@@ -1,0 +1,403 @@
+// Simulation kernels of the hierarchical CVA path (gfx950).
+//
+//   outer_kernel    one lane per outer path: Euler sub-steps of the market factors
+//                   (Appendix B, e:sde1/e:sde2, Q^0 drift of foreign rates), FP64
+//                   trapezoid integrals of r^0 and gamma^{c,+} (rem:finecoarse), and at
+//                   every pricing date the swap book priced by the three-case formula of
+//                   Appendix B, exposures D^c_j = LGD_c beta_j (MtM^c_j)^+, features.
+//   inner_kernel    one lane per outer path, the path's default thresholds staged in LDS:
+//                   the n_b inner draws per counterparty are resolved to a default date by
+//                   the rule of e:tau (Lambda_j >= -log u), counted per date.
+//   targets_kernel  one lane per path: the suffix sums of eq:CVA_portfolio over the date
+//                   histogram give T_i; FP64 block partials give CVA_0 in a fixed order.
+//
+// The outer state is kept in registers for the whole horizon; the only HBM traffic is
+// the per-date outputs.  All parameters that are the same for every lane (Cholesky
+// factor, zero-coupon coefficients, bucketed swap weights) are read with uniform
+// indices, so they come through the scalar cache.
+#include <hip/hip_runtime.h>
+
+#include "philox.hpp"
+#include "sim.hpp"
+
+namespace hsim {
+
+__device__ __forceinline__ float exp_r(float x) { return expf(x); }
+__device__ __forceinline__ double exp_r(double x) { return exp(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+
+template <typename Real, int NE, int NC>
+struct OuterState {
+  Real r[NE];
+  Real x[NE > 1 ? NE - 1 : 1];
+  Real g[NC];
+  Real gcomp[NC];          // rounding error carried by the compensated intensity update
+  Real invzc[NE];          // 1 / ZC^e_{t-}(t-+delta), from r^e at the last reset date
+  double I;
+  double Lam[NC];
+};
+
+// Price the book and emit every per-date output at date i.
+template <typename Real, int NE, int NC>
+__device__ __forceinline__ void price_and_emit(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st,
+                                               int i, int64_t kl) {
+  const int n = a.n_dates;
+  const int q = a.q;
+  const int P2 = a.n_periods + 2;
+  const int64_t M = a.M;
+  const bool reset = (i % q) == 0;
+  const bool coupon = reset && i > 0;
+  const int kfirst = i / q + 1;             // first reset date strictly after t_i
+  // shortest maturity still alive at t_i, and the maturity ending at t_i (if a reset); past
+  // the longest maturity both point at the zero entry n_periods + 1 of the weight tables
+  const int pmin = min((i + q - 1) / q, a.n_periods + 1);
+  const int pnow = min(i / q, a.n_periods + 1);
+
+  Real mtm[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) mtm[c] = (Real)0;
+
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const Real re = st.r[e];
+    const Real* lnA = a.lnA + e * (n + 1);
+    const Real* Bv = a.Bv + e * (n + 1);
+    Real F;
+    if (i == 0) {
+      F = (Real)1;
+    } else if (reset) {
+      F = st.invzc[e];                      // 1 / ZC_{t - delta}(t): the floating coupon
+    } else {
+      const int tau = kfirst * q - i;       // ZC_t(t_+) / ZC_{t_-}(t_+)
+      F = exp_r(lnA[tau] - Bv[tau] * re) * st.invzc[e];
+    }
+    Real acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = (Real)0;
+    for (int kk = kfirst; kk <= a.n_periods; ++kk) {
+      const int tau = kk * q - i;
+      const Real zc = exp_r(lnA[tau] - Bv[tau] * re);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] += zc * a.G[(c * NE + e) * P2 + kk];
+    }
+    const Real fx = (e == 0) ? (Real)1 : exp_r(st.x[e > 0 ? e - 1 : 0]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int base = (c * NE + e) * P2;
+      Real v = F * a.CW1[base + pmin] - acc[c];
+      if (coupon) v -= a.CW2[base + pmin] + a.W1[base + pnow];
+      mtm[c] += fx * v;
+    }
+    if (reset) st.invzc[e] = exp_r(-lnA[q] + Bv[q] * re);
+  }
+
+  const double beta = exp(-st.I);
+  a.I[(int64_t)i * M + kl] = st.I;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t o = ((int64_t)i * NC + c) * M + kl;
+    a.Lam[o] = st.Lam[c];
+    const Real pos = mtm[c] > (Real)0 ? mtm[c] : (Real)0;
+    a.D[o] = (Real)((double)a.lgd[c] * beta * (double)pos);
+    if (a.MtM) a.MtM[o] = mtm[c];
+  }
+  if (a.features) {
+    Real* f = a.features + (int64_t)i * a.n_feat * M + kl;
+    int col = 0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) f[(int64_t)(col++) * M] = st.r[e];
+#pragma unroll
+    for (int e = 1; e < NE; ++e) f[(int64_t)(col++) * M] = st.x[e - 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) f[(int64_t)(col++) * M] = st.g[c];
+    if (a.feature_mode == 1) {
+      double sl = 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sl += st.Lam[c];
+      f[(int64_t)(col++) * M] = (Real)st.I;
+      f[(int64_t)(col++) * M] = (Real)sl;
+    }
+  }
+}
+
+template <typename Real, int NE, int NC>
+__global__ __launch_bounds__(kOuterBlock) __attribute__((amdgpu_waves_per_eu(NE > 4 ? 2 : 4)))
+void outer_kernel(const SimArgs<Real> a) {
+  constexpr int DW = 2 * NE - 1;
+  constexpr int NZ = DW + NC;
+  constexpr int NCALL = (NZ + 3) / 4;
+  const int64_t kl = (int64_t)blockIdx.x * kOuterBlock + threadIdx.x;
+  if (kl >= a.M) return;
+  const uint32_t k = a.path_begin + (uint32_t)kl;
+
+  OuterState<Real, NE, NC> st;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) st.r[e] = a.r0[e];
+#pragma unroll
+  for (int e = 1; e < NE; ++e) st.x[e - 1] = a.x0[e - 1];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    st.g[c] = a.g0[c];
+    st.gcomp[c] = (Real)0;
+    st.Lam[c] = 0.0;
+  }
+  st.I = 0.0;
+  price_and_emit<Real, NE, NC>(a, st, 0, kl);
+
+  for (int i = 0; i < a.n_dates; ++i) {
+    for (int j = 0; j < a.n_sub; ++j) {
+      // Keep the uniform parameters (kernel arguments, Cholesky factor) in memory: they are
+      // re-read through the scalar cache every sub-step instead of being hoisted into
+      // registers, which would cost more registers than the whole path state.
+      asm volatile("" ::: "memory");
+      using CL = CoefLayout<NE, NC>;
+      const Real* cf = a.coef;
+      const Real dt = a.dt;
+      const double hdt = a.half_dt;
+      const uint32_t s = (uint32_t)(i * a.n_sub + j);
+      // Normals arrive four at a time; each market normal z_f is folded at once into the
+      // correlated increments W_p += L_{pf} z_f (p >= f), each CIR normal drives its
+      // intensity step, so only W and the current four normals are live.
+      Real W[DW];
+#pragma unroll
+      for (int p = 0; p < DW; ++p) W[p] = (Real)0;
+#pragma unroll
+      for (int g = 0; g < NCALL; ++g) {
+        Real z[4];
+        normals4<Real>(k, s, (uint32_t)g, a.key0, a.key1, z);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int f = 4 * g + t;
+          if (f < DW) {
+#pragma unroll
+            for (int p = f; p < DW; ++p) W[p] += a.chol[p * (p + 1) / 2 + f] * z[t];
+          } else if (f < NZ) {
+            const int c = f - DW;
+            const Real gp = st.g[c] > (Real)0 ? st.g[c] : (Real)0;
+            // compensated (Fast2Sum) state update: the CIR diffusion amplifies rounding
+            // errors of the state near zero, so the increment's rounding error is carried
+            const Real inc = cf[CL::g_add + c] - cf[CL::g_kd + c] * gp + cf[CL::g_vol + c] * sqrt_r(gp) * z[t]
+                             + st.gcomp[c];
+            const Real gs = st.g[c] + inc;
+            st.gcomp[c] = inc - (gs - st.g[c]);
+            st.g[c] = gs;
+            const Real gn = st.g[c] > (Real)0 ? st.g[c] : (Real)0;
+            st.Lam[c] += hdt * ((double)gp + (double)gn);
+          }
+        }
+      }
+      const Real r0old = st.r[0];
+#pragma unroll
+      for (int e = 1; e < NE; ++e)
+        st.x[e - 1] += (r0old - st.r[e]) * dt + cf[CL::x_add + e - 1] + cf[CL::x_vol + e - 1] * W[NE + e - 1];
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
+        st.r[e] = st.r[e] + cf[CL::r_adt + e] * (cf[CL::r_lvl + e] - st.r[e]) + cf[CL::r_vol + e] * W[e];
+      st.I += hdt * ((double)r0old + (double)st.r[0]);
+    }
+    price_and_emit<Real, NE, NC>(a, st, i + 1, kl);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// inner default draws
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kInnerBlock) void inner_kernel(const InnerArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int lane = threadIdx.x;
+  const int n = a.n_dates;
+  const int C = a.n_cpty;
+  const int64_t M = a.M;
+  const int64_t kl = (int64_t)blockIdx.x * kInnerBlock + lane;
+  const bool valid = kl < M;
+  const uint32_t k = a.path_begin + (uint32_t)kl;
+  const int nb = a.nb_block ? a.nb_block[((int64_t)blockIdx.x * kInnerBlock) / a.block_paths]
+                            : a.n_b;
+  uint32_t* K = lds;                       // [(n+1)][64], column `lane` is private to it
+  uint32_t* cnt = lds + (n + 1) * kInnerBlock;
+
+  for (int c = 0; c < C; ++c) {
+    // Threshold form of the default rule: with u = (2m+1) 2^-24,
+    //   Lambda_j >= -log u  <=>  u >= exp(-Lambda_j)  <=>  m >= ceil((exp(-Lambda_j) 2^24 - 1)/2).
+    for (int j = 0; j <= n; ++j) {
+      uint32_t th = 0xFFFFFFFFu;
+      if (valid) {
+        const double S = exp(-a.Lam[((int64_t)j * C + c) * M + kl]);
+        const double t = ceil((S * 16777216.0 - 1.0) * 0.5);
+        th = t <= 0.0 ? 0u : (uint32_t)t;
+      }
+      K[j * kInnerBlock + lane] = th;
+      cnt[j * kInnerBlock + lane] = 0u;
+    }
+    if (valid) {
+      const uint32_t Kn = K[n * kInnerBlock + lane];
+      for (int l4 = 0; l4 < nb; l4 += 4) {
+        const u32x4 w = philox4x32_10(k, (uint32_t)(l4 >> 2), (uint32_t)c, kTagInner, a.key0, a.key1);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (l4 + t >= nb) break;
+          const uint32_t m = grid23(ws[t]);
+          if (m >= Kn) {                   // defaults by the horizon: smallest j with K_j <= m
+            int lo = 1, hi = n;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (m >= K[mid * kInnerBlock + lane]) hi = mid; else lo = mid + 1;
+            }
+            cnt[lo * kInnerBlock + lane] += 1u;
+          }
+        }
+      }
+      for (int j = 0; j <= n; ++j)
+        a.counts[((int64_t)j * C + c) * M + kl] = (int32_t)cnt[j * kInnerBlock + lane];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// targets and CVA_0
+// ------------------------------------------------------------------------------------
+template <typename Real>
+__global__ __launch_bounds__(kTargetBlock) void targets_kernel(const TargetArgs<Real> a) {
+  __shared__ double red[kTargetBlock];
+  const int64_t M = a.M;
+  const int n = a.n_dates;
+  const int C = a.n_cpty;
+  const int64_t kl = (int64_t)blockIdx.x * kTargetBlock + threadIdx.x;
+  double t0 = 0.0;
+  if (kl < M) {
+    const int nb = a.nb_block ? a.nb_block[kl / a.block_paths] : a.n_b;
+    const double inv_nb = 1.0 / (double)nb;
+    double S = 0.0;                        // sum_{j > i} sum_c D^c_j counts^c_j
+    a.T[(int64_t)n * M + kl] = (Real)0;
+    for (int i = n - 1; i >= 0; --i) {
+      for (int c = 0; c < C; ++c) {
+        const int64_t o = ((int64_t)(i + 1) * C + c) * M + kl;
+        S += (double)a.D[o] * (double)a.counts[o];
+      }
+      const double Ti = S * exp(a.I[(int64_t)i * M + kl]) * inv_nb;
+      a.T[(int64_t)i * M + kl] = (Real)Ti;
+      if (i == 0) t0 = Ti;
+    }
+  }
+  red[threadIdx.x] = t0;
+  __syncthreads();
+  for (int w = kTargetBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kTargetBlock) void reduce_partials(const double* partial, int64_t nblk,
+                                                                double inv_M, double* out) {
+  __shared__ double red[kTargetBlock];
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += kTargetBlock) s += partial[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kTargetBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] * inv_M;
+}
+
+// ------------------------------------------------------------------------------------
+// test hooks
+// ------------------------------------------------------------------------------------
+__global__ void philox_fill_kernel(uint32_t key0, uint32_t key1, uint32_t c1, uint32_t c2, uint32_t c3,
+                                   int64_t k_begin, int64_t count, uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const u32x4 w = philox4x32_10((uint32_t)(k_begin + i), c1, c2, c3, key0, key1);
+  out[4 * i + 0] = w.x;
+  out[4 * i + 1] = w.y;
+  out[4 * i + 2] = w.z;
+  out[4 * i + 3] = w.w;
+}
+
+template <typename Real>
+__global__ void normals_fill_kernel(uint32_t key0, uint32_t key1, int64_t path_begin, int64_t count,
+                                    uint32_t step, int32_t n_z, Real* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t k = (uint32_t)(path_begin + i);
+  for (int g = 0; 4 * g < n_z; ++g) {
+    Real z[4];
+    normals4<Real>(k, step, (uint32_t)g, key0, key1, z);
+    for (int t = 0; t < 4 && 4 * g + t < n_z; ++t) out[i * n_z + 4 * g + t] = z[t];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------
+#define HSIM_SHAPES(X) X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 3) X(10, 8)
+
+bool outer_supported(int n_ccy, int n_cpty) {
+#define X(ne, nc) if (n_ccy == ne && n_cpty == nc) return true;
+  HSIM_SHAPES(X)
+#undef X
+  return false;
+}
+
+template <typename Real>
+hipError_t launch_outer(const SimArgs<Real>& a, hipStream_t stream) {
+  const dim3 grid((unsigned)((a.M + kOuterBlock - 1) / kOuterBlock));
+#define X(ne, nc)                                                                   \
+  if (a.n_ccy == ne && a.n_cpty == nc) {                                            \
+    hipLaunchKernelGGL((outer_kernel<Real, ne, nc>), grid, dim3(kOuterBlock), 0, stream, a); \
+    return hipGetLastError();                                                       \
+  }
+  HSIM_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_inner(const InnerArgs& a, hipStream_t stream) {
+  const dim3 grid((unsigned)((a.M + kInnerBlock - 1) / kInnerBlock));
+  const size_t lds = (size_t)2 * (a.n_dates + 1) * kInnerBlock * sizeof(uint32_t);
+  hipLaunchKernelGGL(inner_kernel, grid, dim3(kInnerBlock), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_targets(const TargetArgs<Real>& a, hipStream_t stream) {
+  const int64_t nblk = (a.M + kTargetBlock - 1) / kTargetBlock;
+  hipLaunchKernelGGL((targets_kernel<Real>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kTargetBlock), 0, stream, a.partial, nblk,
+                     1.0 / (double)a.M, a.cva0);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_fill(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3, int64_t k_begin,
+                              int64_t count, uint32_t* out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(philox_fill_kernel, dim3(blocks), dim3(256), 0, s, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), c1, c2, c3, k_begin, count, out);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_normals_fill(uint64_t seed, int64_t path_begin, int64_t count, int32_t step,
+                               int32_t n_z, Real* out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL((normals_fill_kernel<Real>), dim3(blocks), dim3(256), 0, s, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), path_begin, count, (uint32_t)step, n_z, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_outer<float>(const SimArgs<float>&, hipStream_t);
+template hipError_t launch_outer<double>(const SimArgs<double>&, hipStream_t);
+template hipError_t launch_targets<float>(const TargetArgs<float>&, hipStream_t);
+template hipError_t launch_targets<double>(const TargetArgs<double>&, hipStream_t);
+template hipError_t launch_normals_fill<float>(uint64_t, int64_t, int64_t, int32_t, int32_t, float*,
+                                               hipStream_t);
+template hipError_t launch_normals_fill<double>(uint64_t, int64_t, int64_t, int32_t, int32_t,
+                                                double*, hipStream_t);
+
+}  // namespace hsim

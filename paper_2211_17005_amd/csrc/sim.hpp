@@ -1,0 +1,108 @@
+// Internal interface between the C-ABI layer and the simulation kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsim {
+
+constexpr int kMaxCcy = 16;
+constexpr int kMaxCpty = 16;
+
+// Per-call simulation arguments, passed by value.  Small per-factor Euler coefficients
+// live here; the Cholesky factor, the zero-coupon coefficient tables and the bucketed
+// swap weights live in a device table pointed to by `table`.
+template <typename Real>
+struct SimArgs {
+  int64_t M;              // paths in this call
+  uint32_t path_begin;    // global index of the first path
+  uint32_t key0, key1;    // Philox key
+  int32_t n_ccy, n_cpty;
+  int32_t n_dates, n_sub;
+  int32_t q;              // pricing steps per reset period
+  int32_t n_periods;      // largest maturity in reset periods
+  int32_t feature_mode;   // 0: factors, 1: factors + I + sum Lambda
+  int32_t n_feat;
+  Real dt;
+  double half_dt;
+  Real r0[kMaxCcy], x0[kMaxCcy], g0[kMaxCpty];
+  Real lgd[kMaxCpty];
+  // Euler coefficients, read from device memory inside the sub-step loop:
+  //   r^e      <- r^e + r_adt[e] (r_lvl[e] - r^e) + r_vol[e] * W_e
+  //   log chi^e <- x + (r^0 - r^e) dt + x_add[e-1] + x_vol[e-1] * W_{n_e+e-1}
+  //   gamma^c  <- g + g_add[c] - g_kd[c] g^+ + g_vol[c] sqrt(g^+) z_c
+  // laid out as [r_adt | r_lvl | r_vol]  (n_ccy each), [x_add | x_vol] (n_ccy-1 each),
+  // [g_add | g_kd | g_vol] (n_cpty each); see coef_* offsets below.
+  const Real* coef;
+  // device tables (see TableLayout)
+  const Real* chol;       // packed lower triangle of the market correlation, row by row
+  const Real* lnA;        // [n_ccy][n_dates+1]  Vasicek ln A(tau_j), tau_j = j * horizon / n_dates
+  const Real* Bv;         // [n_ccy][n_dates+1]  Vasicek B(tau_j)
+  const Real* W1;         // [n_cpty][n_ccy][n_periods+2] sum of payer*notional by maturity period
+  const Real* CW1;        // suffix sums of W1 over periods >= p
+  const Real* CW2;        // suffix sums of payer*notional*delta*Sigma over periods >= p
+  const Real* G;          // W1[p] + CW2[p]
+  // outputs
+  Real* features;         // [n+1][n_feat][M] or null
+  double* I;              // [n+1][M]
+  double* Lam;            // [n+1][C][M]
+  Real* D;                // [n+1][C][M]
+  Real* MtM;              // [n+1][C][M] or null
+};
+
+struct InnerArgs {
+  int64_t M;
+  uint32_t path_begin;
+  uint32_t key0, key1;
+  int32_t n_dates, n_cpty;
+  int32_t n_b;                       // uniform n_b when nb_block is null
+  const int32_t* nb_block;           // device [ceil(M/block_paths)] or null
+  int32_t block_paths;
+  const double* Lam;                 // [n+1][C][M]
+  int32_t* counts;                   // [n+1][C][M]
+};
+
+template <typename Real>
+struct TargetArgs {
+  int64_t M;
+  int32_t n_dates, n_cpty;
+  int32_t n_b;
+  const int32_t* nb_block;
+  int32_t block_paths;
+  const double* I;
+  const Real* D;
+  const int32_t* counts;
+  Real* T;                           // [n+1][M]
+  double* partial;                   // [ceil(M / kTargetBlock)]
+  double* cva0;                      // one double
+};
+
+// offsets into SimArgs::coef
+template <int NE, int NC>
+struct CoefLayout {
+  static constexpr int r_adt = 0, r_lvl = NE, r_vol = 2 * NE;
+  static constexpr int x_add = 3 * NE, x_vol = 3 * NE + (NE - 1);
+  static constexpr int g_add = 3 * NE + 2 * (NE - 1), g_kd = g_add + NC, g_vol = g_add + 2 * NC;
+  static constexpr int size = g_add + 3 * NC;
+};
+inline int coef_size(int ne, int nc) { return 3 * ne + 2 * (ne - 1) + 3 * nc; }
+
+constexpr int kOuterBlock = 64;
+constexpr int kInnerBlock = 64;
+constexpr int kTargetBlock = 256;
+
+// Launchers; return hipSuccess or the launch error.  `supported` reports whether a
+// (n_ccy, n_cpty) pair has a compiled instantiation.
+bool outer_supported(int n_ccy, int n_cpty);
+template <typename Real>
+hipError_t launch_outer(const SimArgs<Real>& a, hipStream_t stream);
+hipError_t launch_inner(const InnerArgs& a, hipStream_t stream);
+template <typename Real>
+hipError_t launch_targets(const TargetArgs<Real>& a, hipStream_t stream);
+hipError_t launch_philox_fill(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
+                              int64_t k_begin, int64_t count, uint32_t* out, hipStream_t s);
+template <typename Real>
+hipError_t launch_normals_fill(uint64_t seed, int64_t path_begin, int64_t count, int32_t step,
+                               int32_t n_z, Real* out, hipStream_t s);
+
+}  // namespace hsim

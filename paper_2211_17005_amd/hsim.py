@@ -1,0 +1,336 @@
+"""Python binding of libhsim (the C ABI declared in include/hsim.h).
+
+Argument marshalling only: host parameters go into the C structs, device buffers are
+torch tensors whose pointers are passed through, and every step of the computation runs
+in the library's HIP kernels on the current torch stream.  There is no fallback: if the
+library is not built, or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsim.so")
+
+HSIM_FP64, HSIM_FP32 = 0, 1
+FEAT_FACTORS, FEAT_FACTORS_PLUS = 0, 1
+OP_INNER, OP_TARGETS, OP_FUSED, OP_ADJOINT = 1, 2, 3, 4
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+_c_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class HsimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hsim error {code}: {msg}")
+        self.code = code
+
+
+class Market(ctypes.Structure):
+    _fields_ = [("n_ccy", ctypes.c_int32), ("n_cpty", ctypes.c_int32),
+                ("a", _c_f64p), ("b", _c_f64p), ("sigma_r", _c_f64p), ("r0", _c_f64p),
+                ("sigma_fx", _c_f64p), ("fx0", _c_f64p), ("corr", _c_f64p),
+                ("kappa", _c_f64p), ("theta", _c_f64p), ("nu", _c_f64p),
+                ("lambda0", _c_f64p), ("lgd", _c_f64p)]
+
+
+class Portfolio(ctypes.Structure):
+    _fields_ = [("n_swaps", ctypes.c_int32), ("ccy", _c_i32p), ("cpty", _c_i32p),
+                ("periods", _c_i32p), ("notional", _c_f64p), ("fixed_rate", _c_f64p),
+                ("payer", _c_i32p), ("delta", ctypes.c_double)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("horizon", ctypes.c_double), ("n_dates", ctypes.c_int32),
+                ("n_sub", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhsim.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2211_17005_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                  ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64)
+    M_, P_, G_ = ctypes.POINTER(Market), ctypes.POINTER(Portfolio), ctypes.POINTER(Grid)
+    sig = {
+        "hsim_abi_version": (ctypes.c_int, []),
+        "hsim_last_error": (ctypes.c_char_p, []),
+        "hsim_n_features": (ctypes.c_int, [M_, ctypes.c_int]),
+        "hsim_par_rates": (ctypes.c_int, [M_, P_, _c_f64p]),
+        "hsim_philox_fill": (ctypes.c_int, [u64, u32, u32, u32, i64, i64, vp, vp]),
+        "hsim_normals_fill": (ctypes.c_int, [u64, i64, i64, i32, i32, ctypes.c_int, vp, vp]),
+        "hsim_outer_paths": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, ctypes.c_int, ctypes.c_int,
+                                            vp, vp, vp, vp, vp, vp]),
+        "hsim_inner_defaults": (ctypes.c_int, [G_, i32, u64, i64, i64, i32, vp, i32, vp, vp, vp,
+                                               sz, vp]),
+        "hsim_targets_cva": (ctypes.c_int, [G_, i32, i64, i32, vp, i32, ctypes.c_int, vp, vp, vp,
+                                            vp, vp, vp, sz, vp]),
+        "hsim_inner_defaults_cva": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i32, vp, i32,
+                                                   ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, sz,
+                                                   vp]),
+        "hsim_workspace_bytes": (sz, [ctypes.c_int, M_, G_, i64, ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    _register_extra(L)
+    return L
+
+
+_extra_registrars = []
+
+
+def _register_extra(L):
+    for f in _extra_registrars:
+        f(L)
+
+
+def check(rc: int):
+    if rc != 0:
+        raise HsimError(rc, lib().hsim_last_error().decode())
+
+
+# ------------------------------------------------------------------------------- marshalling
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+
+
+def _i32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(-1))
+
+
+def _ptr(arr, ctype):
+    return arr.ctypes.data_as(ctypes.POINTER(ctype)) if arr.size else None
+
+
+@dataclass
+class _Keep:
+    struct: ctypes.Structure
+    arrays: list
+
+
+def market_struct(m) -> _Keep:
+    arrs = [_f64(getattr(m, f)) for f in ("a", "b", "sigma_r", "r0", "sigma_fx", "fx0", "corr",
+                                          "kappa", "theta", "nu", "lambda0", "lgd")]
+    s = Market(int(arrs[0].size), int(arrs[7].size), *[_ptr(a, ctypes.c_double) for a in arrs])
+    return _Keep(s, arrs)
+
+
+def portfolio_struct(book, fixed_rate) -> _Keep:
+    delta = float(getattr(book, "delta", 1.0))
+    periods = np.rint(np.asarray(book.maturity, dtype=np.float64) / delta).astype(np.int32)
+    arrs = [_i32(book.ccy), _i32(book.cpty), _i32(periods), _f64(book.notional),
+            _f64(fixed_rate), _i32(book.payer)]
+    s = Portfolio(int(arrs[0].size), _ptr(arrs[0], ctypes.c_int32), _ptr(arrs[1], ctypes.c_int32),
+                  _ptr(arrs[2], ctypes.c_int32), _ptr(arrs[3], ctypes.c_double),
+                  _ptr(arrs[4], ctypes.c_double), _ptr(arrs[5], ctypes.c_int32), delta)
+    return _Keep(s, arrs)
+
+
+def grid_struct(g) -> Grid:
+    return Grid(float(g.horizon), int(g.n_dates), int(g.n_sub))
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    """Device pointer of a tensor; the C ABI takes dense row-major arrays only."""
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("libhsim takes contiguous device tensors "
+                         f"(got device={t.device}, strides={tuple(t.stride())})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _expect(t, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected {dtype} {tuple(shape)}, got {t.dtype} {tuple(t.shape)}")
+
+
+def _real(precision):
+    import torch
+    return torch.float32 if precision == HSIM_FP32 else torch.float64
+
+
+# ------------------------------------------------------------------------------- entry points
+def abi_version() -> int:
+    return lib().hsim_abi_version()
+
+
+def n_features(market, feature_mode: int) -> int:
+    k = market_struct(market)
+    n = lib().hsim_n_features(ctypes.byref(k.struct), feature_mode)
+    if n < 0:
+        check(n)
+    return n
+
+
+def par_rates(market, book) -> np.ndarray:
+    km = market_struct(market)
+    kp = portfolio_struct(book, np.zeros(len(book.ccy)))
+    out = np.zeros(len(book.ccy))
+    check(lib().hsim_par_rates(ctypes.byref(km.struct), ctypes.byref(kp.struct),
+                               out.ctypes.data_as(_c_f64p)))
+    return out
+
+
+def fixed_rates(market, book) -> np.ndarray:
+    """Fixed rates of a book given as spreads over the time-0 par rate (library pricing)."""
+    if getattr(book, "fixed_rate", None) is not None:
+        return _f64(book.fixed_rate)
+    return par_rates(market, book) + 1e-4 * _f64(book.spread_bp)
+
+
+def philox_fill(seed: int, c1: int, c2: int, c3: int, k_begin: int, count: int):
+    import torch
+    out = torch.empty(4 * count, dtype=torch.int32, device="cuda")
+    check(lib().hsim_philox_fill(seed, c1, c2, c3, k_begin, count, _dptr(out), _stream()))
+    return out
+
+
+def normals_fill(seed: int, path_begin: int, count: int, step: int, n_z: int, precision: int):
+    import torch
+    out = torch.empty((count, n_z), dtype=_real(precision), device="cuda")
+    check(lib().hsim_normals_fill(seed, path_begin, count, step, n_z, precision, _dptr(out),
+                                  _stream()))
+    return out
+
+
+def feature_mode_of(w) -> int:
+    return FEAT_FACTORS_PLUS if getattr(w, "features", "factors") == "factors_plus" else FEAT_FACTORS
+
+
+def outer_paths(w, precision: int = HSIM_FP32, path_begin: int = 0, M: Optional[int] = None,
+                fixed=None, want_features=True, want_mtm=False, market=None):
+    """hsim_outer_paths on a workload; returns dict of device tensors."""
+    import torch
+    m = w.market if market is None else market
+    M = w.M if M is None else M
+    n1 = w.grid.n_dates + 1
+    C = m.n_cpty
+    fm = feature_mode_of(w)
+    d = n_features(m, fm)
+    R = _real(precision)
+    out = {
+        "features": torch.empty((n1, d, M), dtype=R, device="cuda") if want_features else None,
+        "I": torch.empty((n1, M), dtype=torch.float64, device="cuda"),
+        "Lam": torch.empty((n1, C, M), dtype=torch.float64, device="cuda"),
+        "D": torch.empty((n1, C, M), dtype=R, device="cuda"),
+        "MtM": torch.empty((n1, C, M), dtype=R, device="cuda") if want_mtm else None,
+    }
+    fixed = fixed_rates(m, w.portfolio) if fixed is None else fixed
+    km, kp = market_struct(m), portfolio_struct(w.portfolio, fixed)
+    g = grid_struct(w.grid)
+    check(lib().hsim_outer_paths(ctypes.byref(km.struct), ctypes.byref(kp.struct), ctypes.byref(g),
+                                 w.seed, path_begin, M, precision, fm, _dptr(out["features"]),
+                                 _dptr(out["I"]), _dptr(out["Lam"]), _dptr(out["D"]),
+                                 _dptr(out["MtM"]), _stream()))
+    return out
+
+
+def _nb_args(n_b, n_b_per_block, block_paths):
+    import torch
+    if n_b_per_block is None:
+        return int(n_b), None, 64
+    t = torch.as_tensor(np.asarray(n_b_per_block, dtype=np.int32), device="cuda")
+    return 0, t, int(block_paths)
+
+
+def inner_defaults(grid, n_cpty: int, seed: int, Lam, path_begin: int = 0, n_b: int = 1,
+                   n_b_per_block=None, block_paths: int = 64):
+    import torch
+    M = Lam.shape[-1]
+    _expect(Lam, torch.float64, (grid.n_dates + 1, n_cpty, M), "Lambda")
+    counts = torch.empty((grid.n_dates + 1, n_cpty, M), dtype=torch.int32, device="cuda")
+    nb, nbt, bp = _nb_args(n_b, n_b_per_block, block_paths)
+    g = grid_struct(grid)
+    check(lib().hsim_inner_defaults(ctypes.byref(g), n_cpty, seed, path_begin, M, nb, _dptr(nbt), bp,
+                                    _dptr(Lam), _dptr(counts), None, 0, _stream()))
+    torch.cuda.current_stream().synchronize() if nbt is not None else None
+    return counts
+
+
+def targets_cva(grid, n_cpty: int, I, D, counts, n_b: int = 1, n_b_per_block=None,
+                block_paths: int = 64, precision: int = HSIM_FP32):
+    import torch
+    M = I.shape[-1]
+    _expect(I, torch.float64, (grid.n_dates + 1, M), "I")
+    _expect(D, _real(precision), (grid.n_dates + 1, n_cpty, M), "D")
+    _expect(counts, torch.int32, (grid.n_dates + 1, n_cpty, M), "counts")
+    T = torch.empty((grid.n_dates + 1, M), dtype=_real(precision), device="cuda")
+    cva0 = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = grid_struct(grid)
+    wsb = lib().hsim_workspace_bytes(OP_TARGETS, None, ctypes.byref(g), M, precision)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    nb, nbt, bp = _nb_args(n_b, n_b_per_block, block_paths)
+    check(lib().hsim_targets_cva(ctypes.byref(g), n_cpty, M, nb, _dptr(nbt), bp, precision,
+                                 _dptr(I), _dptr(D), _dptr(counts), _dptr(T), _dptr(cva0),
+                                 _dptr(ws), wsb, _stream()))
+    torch.cuda.current_stream().synchronize() if nbt is not None else None
+    return T, cva0
+
+
+def workspace_bytes(op: int, w, M: int, precision: int) -> int:
+    km = market_struct(w.market)
+    g = grid_struct(w.grid)
+    return int(lib().hsim_workspace_bytes(op, ctypes.byref(km.struct), ctypes.byref(g), M, precision))
+
+
+class Solver:
+    """Holds the marshalled parameters and workspace of one workload for repeated calls."""
+
+    def __init__(self, w, precision: int = HSIM_FP32, M: Optional[int] = None, fixed=None,
+                 n_b_per_block=None, block_paths: int = 64, market=None):
+        import torch
+        self.w = w
+        self.market = w.market if market is None else market
+        self.precision = precision
+        self.M = w.M if M is None else M
+        self.fixed = fixed_rates(self.market, w.portfolio) if fixed is None else fixed
+        self.km = market_struct(self.market)
+        self.kp = portfolio_struct(w.portfolio, self.fixed)
+        self.g = grid_struct(w.grid)
+        self.fm = feature_mode_of(w)
+        self.d = n_features(self.market, self.fm)
+        self.nb, self.nbt, self.bp = _nb_args(w.n_b, n_b_per_block, block_paths)
+        wsb = lib().hsim_workspace_bytes(OP_FUSED, ctypes.byref(self.km.struct),
+                                         ctypes.byref(self.g), self.M, precision)
+        self.wsb = wsb
+        self.ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        R = _real(precision)
+        n1 = w.grid.n_dates + 1
+        self.features = torch.empty((n1, self.d, self.M), dtype=R, device="cuda")
+        self.T = torch.empty((n1, self.M), dtype=R, device="cuda")
+        self.cva0 = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def inner_defaults_cva(self, path_begin: int = 0, want_features: bool = True):
+        check(lib().hsim_inner_defaults_cva(
+            ctypes.byref(self.km.struct), ctypes.byref(self.kp.struct), ctypes.byref(self.g),
+            self.w.seed, path_begin, self.M, self.nb, _dptr(self.nbt), self.bp, self.precision,
+            self.fm, _dptr(self.features if want_features else None), _dptr(self.T),
+            _dptr(self.cva0), _dptr(self.ws), self.wsb, _stream()))
+        return self.features, self.T, self.cva0
+
+
+def inner_defaults_cva(w, precision: int = HSIM_FP32, path_begin: int = 0, M=None,
+                       n_b_per_block=None, block_paths: int = 64):
+    s = Solver(w, precision, M, n_b_per_block=n_b_per_block, block_paths=block_paths)
+    return s.inner_defaults_cva(path_begin)

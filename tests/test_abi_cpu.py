@@ -1,0 +1,142 @@
+"""The C-ABI library loads, exports every declared symbol, and validates arguments on the
+host before any launch (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import model
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hsim.h")
+
+
+@pytest.fixture(scope="module")
+def hs():
+    from paper_2211_17005_amd import hsim
+    if not os.path.exists(hsim.LIB_PATH):
+        pytest.skip("libhsim.so not built")
+    return hsim
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|size_t|const char\*)\s+(\w+)\(", txt, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hsim_outer_paths", "hsim_inner_defaults", "hsim_targets_cva",
+                     "hsim_inner_defaults_cva", "hsim_philox_fill"):
+        assert required in names, required
+
+
+def test_library_exports_every_declared_symbol(hs):
+    L = ctypes.CDLL(hs.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_abi_version(hs):
+    assert hs.abi_version() == 1
+
+
+def test_par_rates_match_oracle(hs):
+    for w in (wl.plain_fp64(), wl.cva_at_scale(M=64), wl.small_multi()):
+        assert np.allclose(hs.par_rates(w.market, w.portfolio), model.par_rates(w), rtol=1e-13,
+                           atol=0)
+
+
+def test_n_features(hs):
+    w = wl.cva_at_scale(M=64)
+    assert hs.n_features(w.market, hs.FEAT_FACTORS) == 27
+    assert hs.n_features(w.market, hs.FEAT_FACTORS_PLUS) == 29
+    assert hs.n_features(wl.plain_fp64().market, hs.FEAT_FACTORS) == 2
+
+
+@pytest.fixture
+def cpu_only():
+    """These calls pass placeholder pointers that validation must reject; never on a GPU."""
+    from conftest import gpu_available
+    if gpu_available():
+        pytest.skip("placeholder-pointer validation tests run on CPU only")
+
+
+def call_outer(hs, w, market=None, book=None, grid=None, M=64, precision=1, fixed=None):
+    m = w.market if market is None else market
+    km = hs.market_struct(m)
+    b = w.portfolio if book is None else book
+    fixed = np.zeros(len(b.ccy)) if fixed is None else fixed
+    kp = hs.portfolio_struct(b, fixed)
+    g = hs.grid_struct(w.grid if grid is None else grid)
+    dummy = ctypes.c_void_p(16)      # never dereferenced: validation fails first
+    rc = hs.lib().hsim_outer_paths(ctypes.byref(km.struct), ctypes.byref(kp.struct),
+                                   ctypes.byref(g), 0, 0, M, precision, 0, None, dummy, dummy,
+                                   dummy, None, None)
+    return rc, hs.lib().hsim_last_error().decode()
+
+
+def test_rejects_bad_arguments_before_launch(hs, cpu_only):
+    w = wl.small_multi()
+    m = w.market
+    # M <= 0
+    rc, msg = call_outer(hs, w, M=0)
+    assert rc == -1 and "M" in msg
+    # correlation not positive definite
+    c = m.corr.copy()
+    c[0, 1] = c[1, 0] = 1.5
+    rc, msg = call_outer(hs, w, market=wl.Market(**{**m.__dict__, "corr": c}))
+    assert rc == -1 and "positive definite" in msg
+    # non-unit diagonal
+    bad2 = wl.Market(**{**m.__dict__, "corr": 2.0 * m.corr})
+    rc, msg = call_outer(hs, w, market=bad2)
+    assert rc == -1 and "diagonal" in msg
+    # a <= 0
+    bad3 = wl.Market(**{**m.__dict__, "a": -m.a})
+    rc, _ = call_outer(hs, w, market=bad3)
+    assert rc == -1
+    # unsupported shape
+    w4 = wl.small_multi(n_ccy=4, n_cpty=4)
+    rc, msg = call_outer(hs, w4)
+    assert rc == -5
+    # maturity beyond the horizon
+    b = wl.Portfolio(**{**w.portfolio.__dict__, "maturity": w.portfolio.maturity + 20})
+    rc, msg = call_outer(hs, w, book=b)
+    assert rc == -1 and "horizon" in msg
+    # reset period not a whole number of steps
+    rc, msg = call_outer(hs, w, grid=wl.Grid(10.0, 15, 2))
+    assert rc == -1 and "whole number" in msg
+    # payer must be +-1
+    b = wl.Portfolio(**{**w.portfolio.__dict__, "payer": np.zeros(w.portfolio.n_swaps, np.int32)})
+    rc, _ = call_outer(hs, w, book=b)
+    assert rc == -1
+    # unknown precision
+    rc, _ = call_outer(hs, w, precision=7)
+    assert rc == -1
+
+
+def test_fused_rejects_small_workspace(hs, cpu_only):
+    w = wl.small_multi()
+    km = hs.market_struct(w.market)
+    kp = hs.portfolio_struct(w.portfolio, np.zeros(w.portfolio.n_swaps))
+    g = hs.grid_struct(w.grid)
+    need = hs.lib().hsim_workspace_bytes(hs.OP_FUSED, ctypes.byref(km.struct), ctypes.byref(g),
+                                         w.M, 1)
+    assert need > 0
+    dummy = ctypes.c_void_p(256)
+    rc = hs.lib().hsim_inner_defaults_cva(ctypes.byref(km.struct), ctypes.byref(kp.struct),
+                                          ctypes.byref(g), 0, 0, w.M, 8, None, 64, 1, 0, None,
+                                          dummy, dummy, dummy, need - 1, None)
+    assert rc == -3
+
+
+def test_inner_rejects_bad_nb(hs, cpu_only):
+    g = hs.grid_struct(wl.Grid(10.0, 50, 25))
+    dummy = ctypes.c_void_p(256)
+    assert hs.lib().hsim_inner_defaults(ctypes.byref(g), 1, 0, 0, 64, 0, None, 64, dummy, dummy,
+                                        None, 0, None) == -2
+    assert hs.lib().hsim_inner_defaults(ctypes.byref(g), 1, 0, 0, 64, 1, dummy, 48, dummy, dummy,
+                                        None, 0, None) == -1

@@ -1,0 +1,210 @@
+"""Parity of the HIP simulation path (outer paths, inner defaults, targets, CVA_0) with the
+FP64 oracle, through the C ABI.
+
+Tolerances
+  * RNG words, uniforms, default counts: bit-exact.
+  * FP64 mode: 1e-12 relative (different operation order and libm only).
+  * FP32 mode: 1e-5 relative for the simulation (state scale-relative; swap values and
+    exposures relative to the gross notional of the netting set, because a swap value is a
+    difference of two legs of notional size).  Default counts in FP32 mode must equal the
+    counts the exact rule gives on the GPU's own Lambda; disagreements with the oracle can
+    only come from draws within 1e-5 (relative) of a threshold and are counted and reported.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import inner as oinner
+from oracle import model, philox, pipeline
+
+pytestmark = pytest.mark.gpu
+
+
+def npy(t):
+    return t.detach().cpu().numpy()
+
+
+def scale_err(got, ref):
+    den = max(float(np.max(np.abs(ref))), 1e-300)
+    return float(np.max(np.abs(got - ref))) / den
+
+
+def gross_notional(w):
+    g = np.zeros(w.market.n_cpty)
+    fx = np.concatenate([[1.0], w.market.fx0])
+    for s in range(w.portfolio.n_swaps):
+        g[w.portfolio.cpty[s]] += w.portfolio.notional[s] * fx[w.portfolio.ccy[s]]
+    return g
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b) if b != 0 else abs(a)
+
+
+def report(name, err, tol):
+    print(f"  {name}: err vs FP64 = {err:.3e} (tol {tol:.0e})", flush=True)
+    assert err <= tol, (name, err, tol)
+
+
+# --------------------------------------------------------------------------------- RNG
+def test_philox_words_bit_exact(lib):
+    for (c1, c2, c3) in ((0, 0, 0), (17, 3, 0), (5, 0, 1), (9, 1, 2)):
+        got = npy(lib.philox_fill(12345, c1, c2, c3, 1000, 1 << 16)).view(np.uint32)
+        ref = philox.raw_words(12345, c1, c2, c3, 1000, 1 << 16)
+        assert np.array_equal(got, ref)
+    # the top of the counter range
+    got = npy(lib.philox_fill((7 << 32) | 3, 1, 2, 3, (1 << 32) - 64, 64)).view(np.uint32)
+    assert np.array_equal(got, philox.raw_words((7 << 32) | 3, 1, 2, 3, (1 << 32) - 64, 64))
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-14), (1, 2e-6)])
+def test_normals_match_oracle(lib, precision, tol):
+    got = npy(lib.normals_fill(0, 100, 4096, 37, 27, precision)).astype(np.float64)
+    ref = philox.outer_normals(0, np.arange(100, 100 + 4096), 37, 27)
+    err = np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref)))
+    report(f"normals precision={precision}", err, tol)
+
+
+# --------------------------------------------------------------------------------- outer
+CASES = [
+    ("plain", lambda: wl.plain_fp64().with_(M=1024)),
+    ("small_multi", lambda: wl.small_multi(M=200)),          # ragged last tile
+    ("tiny", lambda: wl.tiny(M=3)),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    w = request.param[1]()
+    ref = pipeline.simulate(w)
+    return w, ref
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_outer_paths_match_oracle(lib, case, precision):
+    w, ref = case
+    out = lib.outer_paths(w, precision=precision, want_mtm=True)
+    tol = 1e-12 if precision == 0 else 1e-5
+    print(f"[{w.name} precision={precision}]")
+    report("I", scale_err(npy(out["I"]), ref["I"]), tol)
+    report("Lambda", scale_err(npy(out["Lam"]), ref["Lam"]), tol)
+    F, Fr = npy(out["features"]).astype(np.float64), ref["features"]
+    for f in range(F.shape[1]):
+        report(f"feature {f}", scale_err(F[:, f], Fr[:, f]), tol)
+    g = np.maximum(gross_notional(w), 1.0)[None, :, None]
+    mt = npy(out["MtM"]).astype(np.float64)
+    report("MtM / gross notional", float(np.max(np.abs(mt - ref["MtM"]) / g)), tol)
+    D = npy(out["D"]).astype(np.float64)
+    report("D / gross notional", float(np.max(np.abs(D - ref["D"]) / g)), tol)
+
+
+def test_inner_counts_bit_exact_on_oracle_lambda(lib, case):
+    """Fed the oracle's own Lambda, the GPU default counts equal the literal rule's."""
+    import torch
+    w, ref = case
+    Lam = torch.as_tensor(ref["Lam"], device="cuda")
+    cnt = npy(lib.inner_defaults(w.grid, w.market.n_cpty, w.seed, Lam, n_b=w.n_b))
+    assert np.array_equal(cnt, ref["cnt"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_targets_and_cva0_match_oracle(lib, case, precision):
+    w, ref = case
+    feats, T, cva0 = lib.inner_defaults_cva(w, precision=precision)
+    T = npy(T).astype(np.float64)
+    out = lib.outer_paths(w, precision=precision, want_features=False)
+    cnt = npy(lib.inner_defaults(w.grid, w.market.n_cpty, w.seed, out["Lam"], n_b=w.n_b))
+    if precision == 0:
+        assert np.array_equal(cnt, ref["cnt"])
+        report("T", scale_err(T, ref["T"]), 1e-12)
+        report("CVA_0", rel(cva0.item(), ref["cva0"]), 1e-12)
+        return
+    # FP32: the GPU's counts are the exact rule applied to the GPU's Lambda ...
+    u = oinner.inner_draws(w, np.arange(w.M))
+    Lg = np.transpose(npy(out["Lam"]), (0, 2, 1))
+    js = oinner.default_dates(Lg, u)
+    assert np.array_equal(cnt, oinner.default_counts(js, w.grid.n_dates))
+    # ... and every disagreement with the oracle sits inside the guard band
+    js_ref = oinner.default_dates(np.transpose(ref["Lam"], (0, 2, 1)), u)
+    bad = np.argwhere(js != js_ref)
+    eps = -np.log(u)
+    Lr = np.transpose(ref["Lam"], (0, 2, 1))
+    for (k, l, c) in bad:
+        j = min(js[k, l, c], js_ref[k, l, c])
+        lam = Lr[j, k, c]
+        assert abs(lam - eps[k, l, c]) <= 1e-5 * max(lam, eps[k, l, c])
+    print(f"  default draws differing from the oracle (all in the 1e-5 band): {len(bad)}")
+    ok = np.all(cnt == ref["cnt"], axis=(0, 1))
+    report("T (paths with equal counts)", scale_err(T[:, ok], ref["T"][:, ok]), 1e-5)
+    report("CVA_0", rel(cva0.item(), ref["cva0"]), 1e-5 + 2.0 * (~ok).mean())
+
+
+def test_fused_equals_separate_stages(lib):
+    w = wl.small_multi(M=333)
+    for precision in (0, 1):
+        f1, T1, c1 = lib.inner_defaults_cva(w, precision=precision)
+        out = lib.outer_paths(w, precision=precision)
+        cnt = lib.inner_defaults(w.grid, w.market.n_cpty, w.seed, out["Lam"], n_b=w.n_b)
+        T2, c2 = lib.targets_cva(w.grid, w.market.n_cpty, out["I"], out["D"], cnt, n_b=w.n_b,
+                                 precision=precision)
+        assert np.array_equal(npy(f1), npy(out["features"]))
+        assert np.array_equal(npy(T1), npy(T2))
+        assert c1.item() == c2.item()
+
+
+def test_deterministic_and_split_invariant(lib):
+    """Two runs agree bitwise; simulating [0, M/2) and [M/2, M) separately changes nothing."""
+    w = wl.small_multi(M=256)
+    f1, T1, _ = [x.clone() for x in lib.inner_defaults_cva(w, precision=1)]
+    f2, T2, _ = lib.inner_defaults_cva(w, precision=1)
+    assert np.array_equal(npy(f1), npy(f2)) and np.array_equal(npy(T1), npy(T2))
+    half = w.M // 2
+    fa, Ta, _ = [x.clone() for x in lib.inner_defaults_cva(w, precision=1, path_begin=0, M=half)]
+    fb, Tb, _ = lib.inner_defaults_cva(w, precision=1, path_begin=half, M=w.M - half)
+    assert np.array_equal(np.concatenate([npy(Ta), npy(Tb)], axis=1), npy(T1))
+    assert np.array_equal(np.concatenate([npy(fa), npy(fb)], axis=2), npy(f1))
+
+
+def test_uneven_oversimulation_matches_oracle(lib):
+    w = wl.oversim_sweep(M=640, levels=(1, 8, 64, 5, 1024))
+    nbb = w.extra["n_b_per_block"]
+    nbp = np.repeat(nbb, 64)[:w.M]
+    ref = pipeline.simulate(w, n_b_per_path=nbp)
+    _, T, cva0 = lib.inner_defaults_cva(w, precision=0, n_b_per_block=nbb, block_paths=64)
+    report("T (uneven n_b)", scale_err(npy(T), ref["T"]), 1e-12)
+    out = lib.outer_paths(w, precision=0, want_features=False)
+    cnt = npy(lib.inner_defaults(w.grid, 1, w.seed, out["Lam"], n_b_per_block=nbb, block_paths=64))
+    assert np.array_equal(cnt, ref["cnt"])
+
+
+def test_single_path_and_single_draw(lib):
+    w = wl.plain_fp64().with_(M=1, n_b=1)
+    ref = pipeline.simulate(w)
+    _, T, cva0 = lib.inner_defaults_cva(w, precision=0)
+    report("T (M=1, n_b=1)", scale_err(npy(T), ref["T"]) if ref["T"].any() else
+           float(np.max(np.abs(npy(T)))), 1e-12)
+
+
+def test_scale_workload_sampled_paths(lib):
+    """At the full 10-currency / 8-counterparty size and launch shape, sampled paths match."""
+    import torch
+    w = wl.cva_at_scale()
+    s = lib.Solver(w, precision=1)
+    feats, T, cva0 = s.inner_defaults_cva()
+    torch.cuda.synchronize()
+    sample = np.array([0, 1, 63, 64, 4097, 65535, 99999, w.M - 1])
+    fixed = model.fixed_rates(w)
+    o = model.simulate_outer(w, sample)
+    mt = model.mtm(w, o, fixed)
+    F = model.features(w, o)
+    Fg = npy(feats[:, :, torch.as_tensor(sample, device="cuda")]).astype(np.float64)
+    print("[cva_at_scale sampled paths]")
+    for f in range(F.shape[1]):
+        report(f"feature {f}", scale_err(Fg[:, f], F[:, f]), 1e-5)
+    u = oinner.inner_draws(w, sample)
+    js = oinner.default_dates(o.Lam, u)
+    xi = oinner.pathwise_loss(o.I, mt, w.market.lgd, js)
+    Tref = oinner.targets(xi)
+    Tg = npy(T[:, torch.as_tensor(sample, device="cuda")]).astype(np.float64)
+    report("T sampled", scale_err(Tg, Tref), 1e-5)
+    assert np.isfinite(cva0.item()) and cva0.item() > 0
