@@ -199,6 +199,59 @@ enum hsim_op { HSIM_OP_INNER = 1, HSIM_OP_TARGETS = 2, HSIM_OP_FUSED = 3, HSIM_O
 size_t hsim_workspace_bytes(int op, const hsim_market* market, const hsim_grid* grid,
                             int64_t M, int precision);
 
+
+/* ------------------------------------------------------------------------------------------
+ * Regression of the targets on the market state (Section 2: NN^+ search space e:nnp,
+ * BaseAlg = Algorithm 1, Backward learning = Algorithm 2).
+ *
+ * Network: `hidden` ReLU layers of `width` units and a linear output f; prediction
+ * (f)^+ + mu.  Training of one date (BaseAlg with Adam): `epochs` epochs of contiguous
+ * batches of `batch` rows; pos = 0 (no output ReLU) until epoch floor(epochs/2), at the end of
+ * which the output layer is refitted by least squares on the full sample with the hidden layers
+ * frozen and mu fixed, then pos = 1; after every epoch the full-sample pos = 1 loss is computed
+ * and the best parameters are kept.  Inputs are standardised per date (population mean and
+ * standard deviation over the M rows) and targets divided by their root mean square; a date
+ * whose targets are all zero is not trained and predicts 0.  Initial weights are
+ * U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from Philox words (layer, idx >> 2, init_tag, 2) with the
+ * call's seed, biases and mu are 0.  Weights and activations are BF16 on the matrix cores with
+ * FP32 accumulation; master weights, Adam moments, the output layer and the loss are FP32; the
+ * refit is solved in FP64.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t hidden;     /* hidden layers; built shapes (width, hidden): (16,1) (16,2) (32,2) (64,2) (128,3) */
+  int32_t width;      /* units per hidden layer */
+  int32_t d_in;       /* inputs per row, 1..32 (the first d_in features of X) */
+  int32_t epochs;     /* E >= 1 */
+  int32_t batch;      /* rows per SGD batch; the last batch of an epoch may be shorter */
+  float lr, beta1, beta2, eps;  /* Adam */
+  int32_t warm_start; /* 0: every date trains independently from the same initial draw, all dates
+                         in one persistent launch; 1: Backward learning, dates trained one after
+                         another in the order given, each started from the previous date's result */
+  int32_t init_tag;   /* Philox word selecting the initial draw */
+} cva_mlp_cfg;
+
+/* Floats per date of the model array written by cva_regress_fit (parameters, then scaling). */
+int cva_regress_record_floats(const cva_mlp_cfg* cfg);
+
+/* Device workspace for cva_regress_fit. */
+size_t cva_regress_workspace_bytes(const cva_mlp_cfg* cfg, int32_t n_reg, int64_t M);
+
+/* Fit one network per date j < n_reg on rows k < M of
+ *   X_dev [n_dates_total][n_feat][M] (float, the features of hsim_outer_paths) and
+ *   Y_dev [n_dates_total][M] (float, the targets of hsim_targets_cva),
+ * date index dates[j] (host array).  model_dev [n_reg][cva_regress_record_floats] receives
+ * the best parameters and the input scaling; loss_hist_dev [n_reg][epochs] (may be NULL) the
+ * full-sample loss after every epoch (in units of the scaled targets).  n_reg <= 512. */
+int cva_regress_fit(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,
+                    int64_t M, int32_t n_feat, const float* X_dev, const float* Y_dev, uint64_t seed,
+                    float* model_dev, float* loss_hist_dev, void* workspace_dev, size_t ws_bytes,
+                    void* stream);
+
+/* Predictions out_dev [n_reg][M] = ((f)^+ + mu) * y_scale of the fitted networks on X_dev. */
+int cva_regress_predict(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,
+                        int64_t M, int32_t n_feat, const float* X_dev, const float* model_dev,
+                        float* out_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

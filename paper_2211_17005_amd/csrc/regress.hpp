@@ -1,0 +1,63 @@
+// Internal interface of the regression kernels (NN^+ networks trained by BaseAlg).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsim {
+
+constexpr int kMlpThreads = 512;     // 8 waves per workgroup, one workgroup per date
+constexpr int kMlpWaves = kMlpThreads / 64;
+constexpr int kMlpRows = 64;         // rows of a chunk staged in LDS
+constexpr int kMlpDin = 32;          // input width, padded to one MFMA K step
+constexpr int kMaxRegDates = 512;
+
+// Layout of one date's model record (floats):
+//   [ W_1 (U x 32) | b_1 (U) | W_2 (U x U) | b_2 | ... | W_H | b_H | w_out (U) | b_out | mu |
+//     x_mean (32) | x_inv_std (32) | y_scale | trained ]
+// W_1 columns >= d_in stay zero.  Prediction: ((f)^+ + mu) * y_scale, 0 when untrained.
+struct MlpLayout {
+  int U, H;
+  __host__ __device__ int w_off(int l) const {   // l = 1..H
+    return l == 1 ? 0 : U * kMlpDin + U + (l - 2) * (U * U + U);
+  }
+  __host__ __device__ int b_off(int l) const { return w_off(l) + U * (l == 1 ? kMlpDin : U); }
+  __host__ __device__ int wout_off() const { return b_off(H) + U; }
+  __host__ __device__ int bout_off() const { return wout_off() + U; }
+  __host__ __device__ int mu_off() const { return bout_off() + 1; }
+  __host__ __device__ int n_params() const { return mu_off() + 1; }
+  __host__ __device__ int xmean_off() const { return n_params(); }
+  __host__ __device__ int xinv_off() const { return xmean_off() + kMlpDin; }
+  __host__ __device__ int yscale_off() const { return xinv_off() + kMlpDin; }
+  __host__ __device__ int trained_off() const { return yscale_off() + 1; }
+  __host__ __device__ int record() const { return trained_off() + 1; }
+};
+
+struct MlpArgs {
+  int32_t U, H, d_in;
+  int32_t epochs, batch;
+  float lr, beta1, beta2, eps;
+  int32_t n_reg;
+  int64_t M;
+  int32_t n_feat;                 // feature stride of X: X[date][f][k] at (date*n_feat + f)*M + k
+  int32_t init_tag;               // Philox date word of the initial weights
+  uint32_t key0, key1;
+  const float* X;                 // [n+1][n_feat][M]
+  const float* Y;                 // [n+1][M]
+  float* model;                   // [n_reg][record]   (best parameters + scaling)
+  float* cur;                     // [n_reg][n_params] current parameters
+  float* adam_m;                  // [n_reg][n_params]
+  float* adam_v;                  // [n_reg][n_params]
+  double* gram;                   // [n_reg][(U+1)*(U+2)]  refit normal equations
+  float* loss_hist;               // [n_reg][epochs] or null
+  int32_t* queue;                 // work counter (zeroed before the launch)
+  int32_t use_init;               // 1: start from `model` (warm start), 0: from the Philox draw
+  int32_t dates[kMaxRegDates];
+};
+
+hipError_t launch_mlp_stats(const MlpArgs& a, hipStream_t s);
+hipError_t launch_mlp_train(const MlpArgs& a, int n_workgroups, hipStream_t s);
+hipError_t launch_mlp_predict(const MlpArgs& a, float* out, hipStream_t s);
+bool mlp_supported(int U, int H);
+
+}  // namespace hsim

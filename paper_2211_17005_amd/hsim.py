@@ -45,6 +45,13 @@ class Portfolio(ctypes.Structure):
                 ("payer", _c_i32p), ("delta", ctypes.c_double)]
 
 
+class MlpCfg(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("width", ctypes.c_int32), ("d_in", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("warm_start", ctypes.c_int32), ("init_tag", ctypes.c_int32)]
+
+
 class Grid(ctypes.Structure):
     _fields_ = [("horizon", ctypes.c_double), ("n_dates", ctypes.c_int32),
                 ("n_sub", ctypes.c_int32)]
@@ -81,6 +88,12 @@ def lib():
                                                    ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, sz,
                                                    vp]),
         "hsim_workspace_bytes": (sz, [ctypes.c_int, M_, G_, i64, ctypes.c_int]),
+        "cva_regress_record_floats": (ctypes.c_int, [ctypes.POINTER(MlpCfg)]),
+        "cva_regress_workspace_bytes": (sz, [ctypes.POINTER(MlpCfg), i32, i64]),
+        "cva_regress_fit": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32, vp,
+                                           vp, u64, vp, vp, vp, sz, vp]),
+        "cva_regress_predict": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32,
+                                               vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -334,3 +347,48 @@ def inner_defaults_cva(w, precision: int = HSIM_FP32, path_begin: int = 0, M=Non
                        n_b_per_block=None, block_paths: int = 64):
     s = Solver(w, precision, M, n_b_per_block=n_b_per_block, block_paths=block_paths)
     return s.inner_defaults_cva(path_begin)
+
+
+# ------------------------------------------------------------------------------- regression
+def mlp_cfg(mlp, d_in: int, M: int, warm_start: bool = False, init_tag: int = 0) -> MlpCfg:
+    """C config from a workload's MLP settings (batch = M / n_batches when no batch is given)."""
+    batch = int(mlp.batch) if getattr(mlp, "batch", None) else max(1, M // int(mlp.n_batches))
+    return MlpCfg(int(mlp.hidden), int(mlp.width), int(d_in), int(mlp.epochs), batch,
+                  float(mlp.lr), float(mlp.beta1), float(mlp.beta2), float(mlp.eps),
+                  1 if warm_start else 0, int(init_tag))
+
+
+def record_floats(cfg: MlpCfg) -> int:
+    n = lib().cva_regress_record_floats(ctypes.byref(cfg))
+    if n < 0:
+        check(n)
+    return n
+
+
+def regress_fit(cfg: MlpCfg, dates, X, Y, seed: int = 0, want_loss: bool = True):
+    """cva_regress_fit: X [n+1][n_feat][M] float32, Y [n+1][M] float32 (device)."""
+    import torch
+    n1, n_feat, M = X.shape
+    _expect(Y, torch.float32, (n1, M), "Y")
+    _expect(X, torch.float32, (n1, n_feat, M), "X")
+    d = _i32(dates)
+    n_reg = int(d.size)
+    rec = record_floats(cfg)
+    model = torch.zeros((n_reg, rec), dtype=torch.float32, device="cuda")
+    loss = torch.zeros((n_reg, cfg.epochs), dtype=torch.float32, device="cuda") if want_loss else None
+    wsb = lib().cva_regress_workspace_bytes(ctypes.byref(cfg), n_reg, M)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    check(lib().cva_regress_fit(ctypes.byref(cfg), n_reg, d.ctypes.data_as(_c_i32p), n1, M, n_feat,
+                                _dptr(X), _dptr(Y), seed, _dptr(model), _dptr(loss), _dptr(ws), wsb,
+                                _stream()))
+    return model, loss, ws
+
+
+def regress_predict(cfg: MlpCfg, dates, X, model):
+    import torch
+    n1, n_feat, M = X.shape
+    d = _i32(dates)
+    out = torch.empty((int(d.size), M), dtype=torch.float32, device="cuda")
+    check(lib().cva_regress_predict(ctypes.byref(cfg), int(d.size), d.ctypes.data_as(_c_i32p), n1, M,
+                                    n_feat, _dptr(X), _dptr(model), _dptr(out), _stream()))
+    return out

@@ -30,7 +30,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("hsim_outer_paths", "hsim_inner_defaults", "hsim_targets_cva",
-                     "hsim_inner_defaults_cva", "hsim_philox_fill"):
+                     "hsim_inner_defaults_cva", "hsim_philox_fill", "cva_regress_fit",
+                     "cva_regress_predict"):
         assert required in names, required
 
 

@@ -1,0 +1,107 @@
+"""Parity of the BF16 MFMA regression (BaseAlg / Backward learning) with the FP64 oracle fit.
+
+Both sides fit the same inputs: the oracle's own features and targets (FP64 for the oracle,
+rounded to FP32 as the library's input), the same initial draw, batch order and Adam
+hyper-parameters.  The bar is the BF16 regression tolerance: predictions within 2e-2 of the
+FP64 fit, as ||pred - pred64||_2 / ||pred64||_2 and max |pred - pred64| / max |pred64|.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import pipeline
+from oracle import regression as org
+
+pytestmark = pytest.mark.gpu
+TOL = 2e-2
+
+
+def npy(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_errs(got, ref):
+    l2 = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    mx = np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
+    return l2, mx
+
+
+@pytest.fixture(scope="module")
+def data():
+    w = wl.small_multi(M=1024, n_b=16)
+    r = pipeline.simulate(w)
+    return w, r
+
+
+def fit_both(lib, w, r, mlp, dates, warm):
+    import torch
+    X = torch.as_tensor(r["features"].astype(np.float32), device="cuda")
+    Y = torch.as_tensor(r["T"].astype(np.float32), device="cuda")
+    d_in = r["features"].shape[1]
+    cfg = lib.mlp_cfg(mlp, d_in, w.M, warm_start=warm)
+    model, loss, _ = lib.regress_fit(cfg, dates, X, Y, seed=w.seed)
+    pred = npy(lib.regress_predict(cfg, dates, X, model)).astype(np.float64)
+    if warm:
+        fits = org.backward_learning(r["features"], r["T"], mlp, w.seed, dates=dates)
+    else:
+        fits = org.independent_fits(r["features"], r["T"], mlp, w.seed, dates)
+    ref = np.stack([org.predict(fits[i], r["features"][i].T) for i in dates])
+    loss_ref = np.stack([np.array(fits[i].losses) for i in dates])
+    return pred, ref, npy(loss), loss_ref
+
+
+@pytest.mark.parametrize("width,hidden", [(16, 2), (32, 2)])
+def test_independent_fits_match_oracle(lib, data, width, hidden):
+    w, r = data
+    mlp = wl.MLPConfig(hidden=hidden, width=width, epochs=6, batch=256)
+    dates = [3, 10, 15]
+    pred, ref, loss, loss_ref = fit_both(lib, w, r, mlp, dates, warm=False)
+    for j, i in enumerate(dates):
+        l2, mx = rel_errs(pred[j], ref[j])
+        print(f"  date {i} width {width}: l2 {l2:.3e} max {mx:.3e}; loss gpu {loss[j][-1]:.5f} "
+              f"fp64 {loss_ref[j][-1]:.5f}", flush=True)
+        assert l2 <= TOL and mx <= TOL
+
+
+def test_backward_learning_matches_oracle(lib, data):
+    w, r = data
+    mlp = wl.MLPConfig(hidden=2, width=16, epochs=4, batch=256)
+    dates = [12, 11, 10]
+    pred, ref, _, _ = fit_both(lib, w, r, mlp, dates, warm=True)
+    for j, i in enumerate(dates):
+        l2, mx = rel_errs(pred[j], ref[j])
+        print(f"  warm-start date {i}: l2 {l2:.3e} max {mx:.3e}", flush=True)
+        assert l2 <= TOL and mx <= TOL
+
+
+def test_zero_targets_predict_zero_and_ragged_rows(lib):
+    import torch
+    rng = np.random.default_rng(0)
+    M = 200                                    # not a multiple of the 64-row chunk
+    X = rng.standard_normal((3, 5, M)).astype(np.float32)
+    Y = np.abs(rng.standard_normal((3, M))).astype(np.float32)
+    Y[2] = 0.0
+    mlp = wl.MLPConfig(hidden=1, width=16, epochs=2, batch=64)
+    Xt, Yt = torch.as_tensor(X, device="cuda"), torch.as_tensor(Y, device="cuda")
+    cfg = lib.mlp_cfg(mlp, 5, M)
+    model, loss, _ = lib.regress_fit(cfg, [1, 2], Xt, Yt, seed=3)
+    pred = npy(lib.regress_predict(cfg, [1, 2], Xt, model))
+    assert np.all(pred[1] == 0.0)
+    fit = org.fit_date(X[1].T.astype(np.float64), Y[1].astype(np.float64), mlp,
+                       org.init_net(5, 1, 16, 3), 64)
+    ref = org.predict(fit, X[1].T.astype(np.float64))
+    l2, mx = rel_errs(pred[0].astype(np.float64), ref)
+    print(f"  ragged M=200: l2 {l2:.3e} max {mx:.3e}")
+    assert l2 <= TOL and mx <= TOL
+
+
+def test_fit_is_deterministic(lib, data):
+    import torch
+    w, r = data
+    X = torch.as_tensor(r["features"].astype(np.float32), device="cuda")
+    Y = torch.as_tensor(r["T"].astype(np.float32), device="cuda")
+    mlp = wl.MLPConfig(hidden=2, width=16, epochs=2, batch=128)
+    cfg = lib.mlp_cfg(mlp, X.shape[1], w.M)
+    m1, l1, _ = lib.regress_fit(cfg, [5, 6, 7], X, Y)
+    m2, l2, _ = lib.regress_fit(cfg, [5, 6, 7], X, Y)
+    assert torch.equal(m1, m2) and torch.equal(l1, l2)
