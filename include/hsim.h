@@ -218,7 +218,7 @@ size_t hsim_workspace_bytes(int op, const hsim_market* market, const hsim_grid* 
  * refit is solved in FP64.
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
-  int32_t hidden;     /* hidden layers; built shapes (width, hidden): (16,1) (16,2) (32,2) (64,2) (128,3) */
+  int32_t hidden;     /* hidden layers; built shapes (width, hidden): (32,1) (32,2) (64,2) (128,2) (128,3) */
   int32_t width;      /* units per hidden layer */
   int32_t d_in;       /* inputs per row, 1..32 (the first d_in features of X) */
   int32_t epochs;     /* E >= 1 */
@@ -251,6 +251,29 @@ int cva_regress_fit(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates,
 int cva_regress_predict(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,
                         int64_t M, int32_t n_feat, const float* X_dev, const float* model_dev,
                         float* out_dev, void* stream);
+
+
+/* ------------------------------------------------------------------------------------------
+ * Sensitivities of CVA_0.  The differentiated quantity is the smoothed estimator
+ *   CVA_0 = (1/M) sum_k sum_c sum_{j=1}^{n} D^c_j (exp(-Lambda^c_{j-1}) - exp(-Lambda^c_j)),
+ * the exact inner conditional expectation of the pathwise loss of eq:CVA_portfolio (its
+ * indicator form is piecewise constant in the intensity integrals, so its pathwise derivative in
+ * the credit parameters vanishes; Section 4.2 notes the intensity route is the minimal-variance
+ * CVA learner).  Its expectation equals that of hsim_targets_cva's CVA_0.
+ * Parameter order of grad_dev (hsim_n_params entries, 90 for 10 currencies / 8 counterparties):
+ *   r0[n_ccy] fx0[n_ccy-1] lambda0[n_cpty] a[n_ccy] b[n_ccy] sigma_r[n_ccy] sigma_fx[n_ccy-1]
+ *   kappa[n_cpty] theta[n_cpty] nu[n_cpty]
+ * with the swap book's fixed rates held constant.  The forward sweep is the FP32 simulation of
+ * hsim_outer_paths; credit parameters are differentiated by a forward-mode (tangent) sweep of the
+ * CIR scheme, market parameters by a reverse sweep of the Vasicek / log-FX scheme that re-draws
+ * the normals and inverts each Euler sub-step from the state stored at the next pricing date.
+ * cva0_dev: one double; grad_dev: [hsim_n_params] doubles (device).  Workspace:
+ * hsim_workspace_bytes(HSIM_OP_ADJOINT, ...).
+ * ------------------------------------------------------------------------------------------ */
+int hsim_n_params(const hsim_market* market);
+int cva_adjoint(const hsim_market* market, const hsim_portfolio* book, const hsim_grid* grid, uint64_t seed,
+                int64_t path_begin, int64_t M, double* cva0_dev, double* grad_dev, void* workspace_dev,
+                size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -165,11 +165,21 @@ class Adam:
         net.mu -= self.lr * mh / (np.sqrt(vh) + self.eps)
 
 
+REFIT_RIDGE = 1e-4
+
+
 def refit_output_layer(net: Net, X, y) -> None:
-    """Closed-form least squares for (W^{h+1}, b^{h+1}) with frozen hidden layers, mu fixed."""
+    """Closed-form least squares for (W^{h+1}, b^{h+1}) with frozen hidden layers, mu fixed.
+
+    Solved from the normal equations of [H, 1] with a ridge of REFIT_RIDGE times the mean
+    diagonal of the Gram matrix (reading: the hidden features are often nearly collinear and
+    dead ReLU units give zero columns; the ridge makes the closed form well posed).
+    """
     acts, _, _ = forward(net, X)
     H = np.concatenate([acts[-1], np.ones((X.shape[0], 1))], axis=1)
-    sol, *_ = np.linalg.lstsq(H, y - net.mu, rcond=None)
+    G = H.T @ H
+    lam = REFIT_RIDGE * np.trace(G) / G.shape[0]
+    sol = np.linalg.solve(G + lam * np.eye(G.shape[0]), H.T @ (y - net.mu))
     net.W[-1] = sol[:-1][None, :].copy()
     net.b[-1] = np.array([sol[-1]])
 

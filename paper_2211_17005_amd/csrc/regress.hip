@@ -94,8 +94,8 @@ struct Smem {
   static constexpr int SW0 = D + 8;            // padded row strides (bf16 elements)
   static constexpr int SW = U + 8;
   static constexpr int NT = U / 16;
-  static constexpr int w_bytes = (U * SW0 + (H - 1) * U * SW) * 2;
-  static constexpr int a_bytes = (R * SW0 + H * R * SW) * 2;
+  static constexpr int w_bytes = (U * SW0 + (H - 1) * U * SW) * (int)sizeof(__bf16);
+  static constexpr int a_bytes = (R * SW0 + H * R * SW) * (int)sizeof(__bf16);
   static constexpr int f_count = 2 * H * U + 2 * U + 4 * R + 2 * D + 8;
   static constexpr int red_bytes = kMlpThreads * 8;
   static constexpr int bytes = w_bytes + a_bytes + f_count * 4 + red_bytes;
@@ -105,7 +105,7 @@ struct Smem {
     return l == 1 ? base : base + U * SW0 + (l - 2) * U * SW;
   }
   __device__ __bf16* A(int l) const {          // l = 0..H : [R][K + 8]
-    __bf16* a0 = base + w_bytes / 2;
+    __bf16* a0 = base + w_bytes / (int)sizeof(__bf16);
     return l == 0 ? a0 : a0 + R * SW0 + (l - 1) * R * SW;
   }
   __device__ float* F() const { return (float*)((char*)base + w_bytes + a_bytes); }
@@ -154,7 +154,7 @@ __device__ void load_chunk(const Smem<U, H>& S, const MlpArgs& a, int date, int6
       v = (a.X[((int64_t)date * a.n_feat + f) * a.M + r0 + r] - S.xmean()[f]) * S.xinv()[f];
     A0[r * S.SW0 + f] = (__bf16)v;
   }
-  if (opaque_tid() < R) {
+  if (a.Y != nullptr && opaque_tid() < R) {     // prediction has no targets
     const int r = opaque_tid();
     S.ybuf()[r] = r < n ? a.Y[(int64_t)date * a.M + r0 + r] / S.scal()[4] : 0.0f;
   }
@@ -445,9 +445,13 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
   constexpr int NT = U / 16, NG = NT * NT, GS = (NG + kMlpWaves - 1) / kMlpWaves, N = U + 1;
   const int tid = opaque_tid(), wave = tid / 64, lane = tid % 64;
   const int li = lane % 16, lk = 8 * (lane / 16);
-  f32x4 accG[GS];
+  // per-chunk Gram tiles come from the matrix cores in FP32 (exact products of BF16 values,
+  // 64-term sums); the sum over chunks is carried in FP64
+  double accG[GS][4];
 #pragma unroll
-  for (int s = 0; s < GS; ++s) accG[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int s = 0; s < GS; ++s)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) accG[s][v] = 0.0;
   double hs = 0.0, hy = 0.0, ys = 0.0;        // thread u: sum h_u, sum h_u (y - mu); thread U: sum (y - mu)
   const float mu = S.scal()[1];
   for (int64_t r0 = 0; r0 < a.M; r0 += kMlpRows) {
@@ -461,6 +465,7 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
       const int g = kMlpWaves * s + wave;
       if (g >= NG) continue;
       const int ot = g / NT, it = g % NT;
+      f32x4 part = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int k0 = 0; k0 < kMlpRows; k0 += 32) {
         bf16x8 av, bv;
@@ -470,8 +475,10 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
           av[t] = ok ? Hh[(k0 + lk + t) * S.SW + 16 * ot + li] : (__bf16)0.0f;
           bv[t] = ok ? Hh[(k0 + lk + t) * S.SW + 16 * it + li] : (__bf16)0.0f;
         }
-        accG[s] = mfma16(av, bv, accG[s]);
+        part = mfma16(av, bv, part);
       }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) accG[s][v] += (double)part[v];
     }
     if (opaque_tid() < U) {
       const int u = opaque_tid();
@@ -506,12 +513,13 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
   }
   __threadfence_block();
   __syncthreads();
-  // tiny ridge relative to the mean diagonal keeps dead units (zero columns) at weight 0
+  // ridge of kRefitRidge times the mean diagonal: keeps dead units (zero columns) at weight 0 and
+  // bounds the conditioning of the normal equations
   if (opaque_tid() == 0) {
     double tr = 0.0;
 #pragma unroll 1
     for (int i = 0; i < N; ++i) tr += G[i * N + i];
-    const double lam = 1e-9 * tr / N + 1e-300;
+    const double lam = kRefitRidge * tr / N + 1e-300;
 #pragma unroll 1
     for (int i = 0; i < N; ++i) G[i * N + i] += lam;
   }
@@ -731,7 +739,7 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs 
 
 __global__ void fill_i32(int32_t* p, int32_t v) { p[opaque_tid()] = v; }
 
-#define HSIM_MLP_SHAPES(X) X(16, 1) X(16, 2) X(32, 2) X(64, 2) X(128, 3)
+#define HSIM_MLP_SHAPES(X) X(32, 1) X(32, 2) X(64, 2) X(128, 2) X(128, 3)
 
 bool mlp_supported(int U, int H) {
 #define X(u, h) if (U == u && H == h) return true;

@@ -11,6 +11,7 @@ constexpr int kMlpWaves = kMlpThreads / 64;
 constexpr int kMlpRows = 64;         // rows of a chunk staged in LDS
 constexpr int kMlpDin = 32;          // input width, padded to one MFMA K step
 constexpr int kMaxRegDates = 512;
+constexpr double kRefitRidge = 1e-4;  // ridge of the output-layer refit, relative to the mean diagonal
 
 // Layout of one date's model record (floats):
 //   [ W_1 (U x 32) | b_1 (U) | W_2 (U x U) | b_2 | ... | W_H | b_H | w_out (U) | b_out | mu |

@@ -147,6 +147,7 @@ int cva_regress_predict(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* date
   if (rc) return rc;
   if (!X_dev || !model_dev || !out_dev) return fail(HSIM_EINVAL, "X, model and out must not be NULL");
   a.X = X_dev;
+  a.Y = nullptr;
   a.model = (float*)model_dev;
   hipError_t e = launch_mlp_predict(a, out_dev, (hipStream_t)stream);
   return e == hipSuccess ? HSIM_OK : device_error(e, "prediction launch");

@@ -88,6 +88,8 @@ def lib():
                                                    ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, sz,
                                                    vp]),
         "hsim_workspace_bytes": (sz, [ctypes.c_int, M_, G_, i64, ctypes.c_int]),
+        "hsim_n_params": (ctypes.c_int, [M_]),
+        "cva_adjoint": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, vp, vp, vp, sz, vp]),
         "cva_regress_record_floats": (ctypes.c_int, [ctypes.POINTER(MlpCfg)]),
         "cva_regress_workspace_bytes": (sz, [ctypes.POINTER(MlpCfg), i32, i64]),
         "cva_regress_fit": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32, vp,
@@ -392,3 +394,76 @@ def regress_predict(cfg: MlpCfg, dates, X, model):
     check(lib().cva_regress_predict(ctypes.byref(cfg), int(d.size), d.ctypes.data_as(_c_i32p), n1, M,
                                     n_feat, _dptr(X), _dptr(model), _dptr(out), _stream()))
     return out
+
+
+# ------------------------------------------------------------------------------- sensitivities
+PARAM_FIELDS = ("r0", "fx0", "lambda0", "a", "b", "sigma_r", "sigma_fx", "kappa", "theta", "nu")
+
+
+def n_params(market) -> int:
+    k = market_struct(market)
+    n = lib().hsim_n_params(ctypes.byref(k.struct))
+    if n < 0:
+        check(n)
+    return n
+
+
+class Adjoint:
+    """Holds the workspace of cva_adjoint for one workload; call() returns (cva0, grad) tensors."""
+
+    def __init__(self, w, M: Optional[int] = None, fixed=None):
+        import torch
+        self.w = w
+        self.M = w.M if M is None else M
+        self.fixed = fixed_rates(w.market, w.portfolio) if fixed is None else fixed
+        self.kp = portfolio_struct(w.portfolio, self.fixed)
+        self.g = grid_struct(w.grid)
+        km = market_struct(w.market)
+        self.wsb = lib().hsim_workspace_bytes(OP_ADJOINT, ctypes.byref(km.struct), ctypes.byref(self.g),
+                                              self.M, HSIM_FP32)
+        self.ws = torch.empty(self.wsb, dtype=torch.uint8, device="cuda")
+        self.P = n_params(w.market)
+        self.cva0 = torch.empty(1, dtype=torch.float64, device="cuda")
+        self.grad = torch.empty(self.P, dtype=torch.float64, device="cuda")
+
+    def __call__(self, market=None, path_begin: int = 0):
+        km = market_struct(self.w.market if market is None else market)
+        check(lib().cva_adjoint(ctypes.byref(km.struct), ctypes.byref(self.kp.struct), ctypes.byref(self.g),
+                                self.w.seed, path_begin, self.M, _dptr(self.cva0), _dptr(self.grad),
+                                _dptr(self.ws), self.wsb, _stream()))
+        return self.cva0, self.grad
+
+
+def pack_params(market) -> np.ndarray:
+    return np.concatenate([np.asarray(getattr(market, f), dtype=np.float64).reshape(-1) for f in PARAM_FIELDS])
+
+
+def unpack_params(market, vec):
+    import dataclasses
+    kw, o = {}, 0
+    for f in PARAM_FIELDS:
+        k = len(np.asarray(getattr(market, f)).reshape(-1))
+        kw[f] = np.array(vec[o:o + k], dtype=np.float64)
+        o += k
+    return dataclasses.replace(market, **kw)
+
+
+def cva_function():
+    """torch.autograd.Function: CVA_0(params) with params a CPU float64 vector in the order of
+    PARAM_FIELDS; backward uses the library's adjoint gradient."""
+    import torch
+
+    class CVA(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, params, adj):
+            m = unpack_params(adj.w.market, params.detach().cpu().numpy())
+            cva0, grad = adj(m)
+            ctx.save_for_backward(grad.detach().cpu().clone())
+            return cva0.detach().cpu().clone()[0]
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            return gout * grad, None
+
+    return CVA

@@ -68,14 +68,30 @@ def test_first_adam_step_moves_by_signed_lr():
 
 
 def test_output_refit_is_stationary():
-    """After the closed-form refit, the pos=0 gradient in (W^{h+1}, b^{h+1}) vanishes."""
+    """After the closed-form refit, the gradient of the ridge-penalised pos=0 loss in
+    (W^{h+1}, b^{h+1}) vanishes, and with the ridge switched off the refit is the OLS fit."""
     X, y = rand_problem(M=200)
     net = rg.init_net(3, 2, 6, seed=5)
     net.mu = 0.3
     rg.refit_output_layer(net, X, y)
     gW, gb, _ = rg.grads(net, X, y, 0)
-    assert np.max(np.abs(gW[-1])) < 1e-10
-    assert abs(gb[-1][0]) < 1e-10
+    acts, _, _ = rg.forward(net, X)
+    H = np.concatenate([acts[-1], np.ones((X.shape[0], 1))], axis=1)
+    G = H.T @ H
+    lam = rg.REFIT_RIDGE * np.trace(G) / G.shape[0]
+    # d/dw [ (1/M) |H w + mu - y|^2 + (lam/M) |w|^2 ] = grads + 2 lam w / M
+    w = np.concatenate([net.W[-1][0], net.b[-1]])
+    pen = 2.0 * lam * w / X.shape[0]
+    assert np.max(np.abs(gW[-1][0] + pen[:-1])) < 1e-10
+    assert abs(gb[-1][0] + pen[-1]) < 1e-10
+    old = rg.REFIT_RIDGE
+    try:
+        rg.REFIT_RIDGE = 0.0
+        rg.refit_output_layer(net, X, y)
+    finally:
+        rg.REFIT_RIDGE = old
+    sol, *_ = np.linalg.lstsq(H, y - net.mu, rcond=None)
+    assert np.allclose(np.concatenate([net.W[-1][0], net.b[-1]]), sol, rtol=1e-8, atol=1e-10)
 
 
 def test_linear_network_converges_to_ols():

@@ -226,7 +226,7 @@ def tiny(seed: int = 0, n_ccy: int = 2, n_cpty: int = 2, n_swaps: int = 3,
     book = random_book(rng, n_swaps, n_ccy, n_cpty, max_maturity=int(horizon))
     return Workload(name="tiny", market=mkt, portfolio=book,
                     grid=Grid(horizon, n_dates, n_sub), M=M, n_b=n_b, seed=seed,
-                    mlp=MLPConfig(hidden=1, width=16, epochs=4, n_batches=2))
+                    mlp=MLPConfig(hidden=1, width=32, epochs=4, n_batches=2))
 
 
 def small_multi(seed: int = 0, M: int = 256, n_b: int = 8, n_ccy: int = 3, n_cpty: int = 3,
@@ -239,7 +239,7 @@ def small_multi(seed: int = 0, M: int = 256, n_b: int = 8, n_ccy: int = 3, n_cpt
     return Workload(name=f"small_{n_ccy}ccy_{n_cpty}cpty_M{M}", market=mkt, portfolio=book,
                     grid=Grid(horizon, n_dates, n_sub), M=M, n_b=n_b, seed=seed,
                     features="factors_plus",
-                    mlp=MLPConfig(hidden=2, width=16, epochs=6, n_batches=4))
+                    mlp=MLPConfig(hidden=2, width=32, epochs=6, n_batches=4))
 
 
 def get(name: str, **kw) -> Workload:
