@@ -1,22 +1,26 @@
 """Benchmark of the hierarchical-simulation CVA path on one MI355X.
 
-One step = one pass of the hot path over the 10-currency / 9-FX / 8-counterparty /
-500-swap workload (100 pricing dates x 25 Euler sub-steps over 10y, M = 2^17 outer paths,
-n_b = 128 inner default draws per path and counterparty), FP32 simulation with FP64
-integrals:
-  outer paths + pricing  ->  inner default draws  ->  targets and CVA_0
-  [-> batched regression of the targets at every date]  [-> adjoint sensitivities]
-with the stages that are built.  The metric is outer x inner path-steps per second:
+One step = one pass of the whole hot path (one CVA-with-sensitivities solve) on the
+ten-currency / nine-FX / eight-counterparty / 500-swap workload (100 pricing dates x 25 Euler
+sub-steps over 10y, FP32 simulation with FP64 integrals):
+  1. M = 2^17 outer paths + pricing -> n_b = 128 inner default draws -> targets and CVA_0;
+  2. NN^+ regression of the targets at all 100 dates in one persistent launch (3 x 128 ReLU,
+     29 inputs, BF16 on the matrix cores, batch 8192, 50 epochs);
+  3. CVA_0 sensitivities to the 90 model inputs by the tangent/adjoint sweeps (M = 2^16).
+The metric is outer x inner path-steps per second of the whole step:
 M * n_b * n_dates / (seconds per step).
 
-Prints one JSON line.  The CPU baseline (the FP64 oracle on a bounded sample of the
-same workload, in worker processes on the host cores) runs before the GPU is touched.
+Also reported: per-stage times (HIP events on the launch stream), the roofline of the
+dominant kernel (and of the simulation kernel), the plain-FP32 comparison solve (same
+simulation, sequential per-date FP32 regression in plain PyTorch, sensitivities by central
+finite differences with common random numbers), and the FP64 oracle on the host cores.
+
+Prints one JSON line.  The CPU baseline runs before the GPU is touched.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,9 +33,10 @@ import numpy as np  # noqa: E402
 
 import workloads as wl  # noqa: E402
 
-# MI355X figures used for the roofline (AMD specifications and unit counts)
+# MI355X figures used for the rooflines (AMD specifications and unit counts)
 N_CU, CLOCK_HZ, LANES_PER_CU_CLK = 256, 2.4e9, 64
 VALU_PEAK_OPS = N_CU * CLOCK_HZ * LANES_PER_CU_CLK          # 39.3e12 VALU lane-ops/s
+BF16_PEAK = 2.5e15                                           # dense BF16 matrix FLOP/s
 HBM_PEAK = 8.0e12
 
 
@@ -59,12 +64,18 @@ def outer_ops_per_path(w) -> dict:
     return {"substep": sub, "total": S * sub + price}
 
 
-def outer_bytes_per_path(w, real_bytes=4) -> int:
-    """Algorithmic HBM bytes one outer path writes: features, I, Lambda, D."""
-    n1 = w.grid.n_dates + 1
-    d = wl.n_features(w)
-    C = w.market.n_cpty
-    return n1 * (d * real_bytes + 8 + C * 8 + C * real_bytes)
+def mlp_flops_per_date(d_in: int, width: int, hidden: int, M: int, epochs: int) -> float:
+    """Algorithmic FLOPs of BaseAlg on one date (FMA = 2).
+
+    Per row and SGD step: forward 2(d U + (H-1) U^2 + U), weight gradients
+    2(d U + (H-1) U^2), hidden-layer back-propagation 2 (H-1) U^2, output layer 2U.
+    Per epoch one full-sample forward pass; at the refit one forward pass plus the
+    (U+1)^2 Gram matrix.
+    """
+    U, H, d = width, hidden, d_in
+    fwd = 2.0 * (d * U + (H - 1) * U * U + U)
+    train = fwd + 2.0 * (d * U + (H - 1) * U * U) + 2.0 * (H - 1) * U * U + 2.0 * U
+    return epochs * M * (train + fwd) + M * (fwd + 2.0 * (U + 1) ** 2)
 
 
 # ------------------------------------------------------------------------------- CPU baseline
@@ -89,20 +100,81 @@ def cpu_baseline(w, name, kw, paths_per_worker: int, workers: int):
     n_paths = workers * paths_per_worker
     rate = n_paths * w.n_b * w.grid.n_dates / wall
     return {"value": rate, "unit": "path-steps/s", "cores": workers, "kind": "oracle",
-            "sample": f"{n_paths} outer paths x n_b={w.n_b} of the same workload "
-                      f"(simulation, pricing, inner draws, targets), FP64 NumPy, "
-                      f"{workers} processes, wall {wall:.1f} s"}
+            "sample": f"{n_paths} outer paths x n_b={w.n_b} of the same workload (simulation, "
+                      f"pricing, inner draws, targets; the regression and sensitivities are not "
+                      f"in the sample), FP64 NumPy, {workers} processes, wall {wall:.1f} s"}
+
+
+# ------------------------------------------------------------------------------- plain FP32
+def plain_regression_fp32(X, Y, mlp, dates, seed):
+    """Comparator: BaseAlg + Backward learning in plain FP32 PyTorch, one date after another."""
+    import torch
+    from oracle import regression as org     # initial draw only (same as the library's)
+    dev = X.device
+    d_in = X.shape[1]
+    M = X.shape[2]
+    batch = mlp.batch
+    net0 = org.init_net(d_in, mlp.hidden, mlp.width, seed)
+    Ws = [torch.tensor(w, dtype=torch.float32, device=dev) for w in net0.W]
+    bs = [torch.zeros(w.shape[0], dtype=torch.float32, device=dev) for w in net0.W]
+    mu = torch.zeros((), dtype=torch.float32, device=dev)
+    for i in dates:
+        x = X[i].T
+        y = Y[i]
+        xs = (x - x.mean(0)) / x.std(0, unbiased=False).clamp_min(1e-30)
+        ys = torch.sqrt((y * y).mean())
+        yn = y / ys
+        params = [p.clone().requires_grad_(True) for p in Ws + bs] + [mu.clone().requires_grad_(True)]
+        opt = torch.optim.Adam(params, lr=mlp.lr, betas=(mlp.beta1, mlp.beta2), eps=mlp.eps)
+        H = mlp.hidden
+
+        def f(xx, p):
+            a = xx
+            for l in range(H):
+                a = torch.relu(a @ p[l].T + p[H + 1 + l])
+            return (a @ p[H].T + p[2 * H + 1])[:, 0], a
+
+        best, pos = float("inf"), 0
+        for epoch in range(1, mlp.epochs + 1):
+            for s in range(0, M, batch):
+                out, _ = f(xs[s:s + batch], params)
+                pred = (torch.relu(out) if pos else out) + params[-1]
+                loss = ((pred - yn[s:s + batch]) ** 2).mean()
+                opt.zero_grad()
+                loss.backward()
+                opt.step()
+            with torch.no_grad():
+                if epoch == mlp.epochs // 2:
+                    _, a = f(xs, params)
+                    A = torch.cat([a, torch.ones_like(a[:, :1])], 1)
+                    G = A.T @ A
+                    lam = 1e-4 * torch.trace(G) / G.shape[0]
+                    sol = torch.linalg.solve(G + lam * torch.eye(G.shape[0], device=dev),
+                                             A.T @ (yn - params[-1]))
+                    params[H].copy_(sol[:-1][None, :])
+                    params[2 * H + 1].copy_(sol[-1:])
+                    pos = 1
+                out, _ = f(xs, params)
+                L = float((((torch.relu(out)) + params[-1] - yn) ** 2).mean())
+                if L < best:
+                    best = L
+                    kept = [p.detach().clone() for p in params]
+        Ws, bs, mu = kept[:H + 1], kept[H + 1:2 * H + 2], kept[-1]
+    torch.cuda.synchronize()
 
 
 # ------------------------------------------------------------------------------- GPU step
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--M", type=int, default=1 << 17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--sim-only", action="store_true", help="time the simulation stages only")
     ap.add_argument("--cpu-paths-per-worker", type=int, default=96)
+    ap.add_argument("--plain-dates", type=int, default=2)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -113,6 +185,8 @@ def main():
 
     name, kw = "cva_at_scale", {"M": args.M}
     w = wl.get(name, **kw)
+    wr = wl.precision_form(M=args.M)                 # regression settings on the same market
+    wa = wl.differentiation_form()                   # sensitivities: same market, M = 2^16
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -147,46 +221,107 @@ def main():
     P = hsim._dptr
     by = hsim.ctypes.byref
 
+    dates = list(range(1, w.grid.n_dates + 1))
+    cfg = hsim.mlp_cfg(wr.mlp, d, M)
+    rec = hsim.record_floats(cfg)
+    model = torch.zeros((len(dates), rec), dtype=torch.float32, device="cuda")
+    mws = L.cva_regress_workspace_bytes(by(cfg), len(dates), M)
+    mws_t = torch.empty(mws, dtype=torch.uint8, device="cuda")
+    dates_c = np.asarray(dates, dtype=np.int32)
+    adj = hsim.Adjoint(wa, fixed=fixed)
+
+    stages = ["outer", "inner", "targets"] + ([] if args.sim_only else ["regression", "adjoint"])
+
     def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
+        def mark(k):
+            if ev is not None:
+                ev[k].record(stream)
+        mark(0)
         hsim.check(L.hsim_outer_paths(by(km.struct), by(kp.struct), by(g), w.seed, 0, M, prec, fm,
                                       P(feats), P(I), P(Lam), P(D), None, hsim._stream()))
-        if ev is not None:
-            ev[1].record(stream)
+        mark(1)
         hsim.check(L.hsim_inner_defaults(by(g), C, w.seed, 0, M, w.n_b, None, 64, P(Lam), P(cnt),
                                          None, 0, hsim._stream()))
-        if ev is not None:
-            ev[2].record(stream)
+        mark(2)
         hsim.check(L.hsim_targets_cva(by(g), C, M, w.n_b, None, 64, prec, P(I), P(D), P(cnt),
                                       P(T), P(cva0), P(ws), wsb, hsim._stream()))
-        if ev is not None:
-            ev[3].record(stream)
+        mark(3)
+        if args.sim_only:
+            return
+        hsim.check(L.cva_regress_fit(by(cfg), len(dates), dates_c.ctypes.data_as(hsim._c_i32p), n1, M, d,
+                                     P(feats), P(T), w.seed, P(model), None, P(mws_t), mws,
+                                     hsim._stream()))
+        mark(4)
+        adj()
+        mark(5)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+           for _ in range(args.steps)]
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
     start.record(stream)
     for k in range(args.steps):
         step(evs[k])
+        print(f"# step {k} done", file=sys.stderr, flush=True)
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = start.elapsed_time(end) / args.steps
-    outer_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    inner_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    targ_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    stage_ms = {s: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
+                for i, s in enumerate(stages)}
 
     path_steps = M * w.n_b * w.grid.n_dates
     value = path_steps / (ms_step / 1e3)
     ops = outer_ops_per_path(w)["total"] * M
-    achieved = ops / (outer_ms / 1e3)
-    rec = {
-        "metric": "outer x inner path-steps/s (hierarchical CVA simulation, 1 GPU)",
+    outer_roof = {"bound": "alu", "kernel": "outer_kernel<float,10,8>",
+                  "achieved": ops / (stage_ms["outer"] / 1e3) / 1e12,
+                  "peak": VALU_PEAK_OPS / 1e12, "unit": "T VALU lane-ops/s",
+                  "frac": ops / (stage_ms["outer"] / 1e3) / VALU_PEAK_OPS, "traffic": None}
+    roof = outer_roof
+    mlp_roof = None
+    if not args.sim_only:
+        fl = mlp_flops_per_date(wl.n_features(w), wr.mlp.width, wr.mlp.hidden, M, wr.mlp.epochs)
+        fl *= w.grid.n_dates - 1          # the last date has zero targets and is not trained
+        mlp_roof = {"bound": "mfma", "kernel": "mlp_train_kernel<128,3> (+ stats)",
+                    "achieved": fl / (stage_ms["regression"] / 1e3) / 1e12,
+                    "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s",
+                    "frac": fl / (stage_ms["regression"] / 1e3) / BF16_PEAK, "traffic": None}
+        if stage_ms["regression"] > stage_ms["outer"]:
+            roof = mlp_roof
+
+    plain = None
+    if not args.sim_only and not args.no_plain:
+        # plain FP32 form: same simulation; sequential FP32 regression in PyTorch (timed on a
+        # few dates and scaled to all of them); sensitivities by CRN central differences
+        pd = list(range(w.grid.n_dates - 1, w.grid.n_dates - 1 - args.plain_dates, -1))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plain_regression_fp32(feats, T, wr.mlp, pd, w.seed)
+        reg_s = (time.perf_counter() - t) * (w.grid.n_dates - 1) / len(pd)
+        base = hsim.pack_params(wa.market)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(base.size):
+            h = 1e-3 * abs(base[k]) if base[k] != 0 else 1e-4
+            for sgn in (1.0, -1.0):
+                v = base.copy()
+                v[k] += sgn * h
+                adj(hsim.unpack_params(wa.market, v), with_grad=False)
+        torch.cuda.synchronize()
+        fd_s = time.perf_counter() - t
+        sim_s = (stage_ms["outer"] + stage_ms["inner"] + stage_ms["targets"]) / 1e3
+        plain_s = sim_s + reg_s + fd_s
+        plain = {"solve_s": plain_s, "simulation_s": sim_s,
+                 "regression_s": reg_s, "regression_note": f"timed on {len(pd)} dates, scaled to "
+                 f"{w.grid.n_dates - 1}", "sensitivities_s": fd_s,
+                 "speedup_of_fast_form": plain_s / (ms_step / 1e3)}
+
+    rec_out = {
+        "metric": "outer x inner path-steps/s of the whole CVA-with-sensitivities solve (1 GPU)",
         "value": value,
         "unit": "path-steps/s",
         "n_gpus": 1,
@@ -196,23 +331,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 integrals)",
+        "dtype": "f32 simulation (f64 integrals), bf16 regression",
         "data": "synthetic (seeded model parameters, LKJ(2) correlation, random swap book)",
         "config": {"workload": w.name, "n_ccy": w.market.n_ccy, "n_cpty": C,
                    "n_swaps": w.portfolio.n_swaps, "n_dates": w.grid.n_dates,
-                   "n_sub": w.grid.n_sub, "M": M, "n_b": w.n_b,
-                   "stages": ["outer+pricing", "inner defaults", "targets+CVA_0"]},
-        "stage_ms": {"outer_kernel": outer_ms, "inner_kernel": inner_ms,
-                     "targets_kernels": targ_ms},
-        "roofline": {"bound": "alu", "kernel": "outer_kernel<float,10,8>",
-                     "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "T VALU lane-ops/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": None},
+                   "n_sub": w.grid.n_sub, "M": M, "n_b": w.n_b, "stages": stages,
+                   "regression": {"dates": len(dates), "hidden": wr.mlp.hidden,
+                                  "width": wr.mlp.width, "inputs": d, "batch": wr.mlp.batch,
+                                  "epochs": wr.mlp.epochs},
+                   "sensitivities": {"M": wa.M, "inputs": int(hsim.n_params(wa.market))}},
+        "stage_ms": stage_ms,
+        "solve_s": ms_step / 1e3,
+        "roofline": roof,
+        "roofline_simulation": outer_roof,
+        "roofline_regression": mlp_roof,
         "cva0": cva0.item(),
+        "plain_fp32": plain,
         "cpu_baseline": cpu,
         "wall_s": wall,
     }
-    print(json.dumps(rec), flush=True)
+    print(json.dumps(rec_out), flush=True)
 
 
 if __name__ == "__main__":

@@ -408,15 +408,29 @@ __global__ __launch_bounds__(256) void adj_reduce(const double* gp, int64_t M, i
   }
 }
 
+__global__ __launch_bounds__(256) void adj_reduce_one(const double* row, int64_t M, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < M; k += 256) s += row[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] / (double)M;
+}
+
 #define HSIM_ADJ_SHAPES(X) X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 3) X(10, 8)
 
-hipError_t launch_adjoint(const AdjArgs& a, hipStream_t stream) {
+hipError_t launch_adjoint(const AdjArgs& a, bool with_grad, hipStream_t stream) {
   const dim3 grid((unsigned)((a.sim.M + kOuterBlock - 1) / kOuterBlock));
   bool done = false;
 #define X(ne, nc)                                                                                  \
   if (!done && a.sim.n_ccy == ne && a.sim.n_cpty == nc) {                                          \
     hipLaunchKernelGGL((credit_kernel<ne, nc>), grid, dim3(kOuterBlock), 0, stream, a);            \
-    hipLaunchKernelGGL((market_adjoint_kernel<ne, nc>), grid, dim3(kOuterBlock), 0, stream, a);    \
+    if (with_grad)                                                                                 \
+      hipLaunchKernelGGL((market_adjoint_kernel<ne, nc>), grid, dim3(kOuterBlock), 0, stream, a);  \
     done = true;                                                                                   \
   }
   HSIM_ADJ_SHAPES(X)
@@ -424,8 +438,12 @@ hipError_t launch_adjoint(const AdjArgs& a, hipStream_t stream) {
   if (!done) return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adj_reduce, dim3(a.par.n_params + 1), dim3(256), 0, stream, a.grad_path, a.sim.M,
-                     a.par.n_params, a.grad_out, a.cva0_out);
+  if (with_grad)
+    hipLaunchKernelGGL(adj_reduce, dim3(a.par.n_params + 1), dim3(256), 0, stream, a.grad_path, a.sim.M,
+                       a.par.n_params, a.grad_out, a.cva0_out);
+  else                                    // the J row only
+    hipLaunchKernelGGL(adj_reduce_one, dim3(1), dim3(256), 0, stream, a.grad_path + (int64_t)a.par.n_params * a.sim.M,
+                       a.sim.M, a.cva0_out);
   return hipGetLastError();
 }
 

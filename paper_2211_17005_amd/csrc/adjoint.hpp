@@ -40,10 +40,11 @@ struct AdjArgs {
   float dt_f, sqrt_dt;
   AdjParams par;
   double* grad_path;             // [n_params + 1][M]: per-path gradient rows, then J
-  double* grad_out;              // [n_params]
+  double* grad_out;              // [n_params] or null
   double* cva0_out;              // one double
 };
 
-hipError_t launch_adjoint(const AdjArgs& a, hipStream_t stream);
+// with_grad = false: CVA_0 only (the credit sweep computes J; no market sweep, no gradient)
+hipError_t launch_adjoint(const AdjArgs& a, bool with_grad, hipStream_t stream);
 
 }  // namespace hsim

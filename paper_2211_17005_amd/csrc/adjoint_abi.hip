@@ -66,7 +66,7 @@ int cva_adjoint(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* 
   memset(&a, 0, sizeof(a));
   int rc = build_sim_args<float>(m, p, g, seed, path_begin, M, HSIM_FEAT_FACTORS, a.sim);
   if (rc) return rc;
-  if (!cva0_dev || !grad_dev) return fail(HSIM_EINVAL, "cva0 and grad must not be NULL");
+  if (!cva0_dev) return fail(HSIM_EINVAL, "cva0 must not be NULL");
   const AdjLayout L = adj_layout(m, g, M);
   if (!workspace_dev || ws_bytes < L.total) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, L.total);
   char* w = (char*)workspace_dev;
@@ -121,7 +121,7 @@ int cva_adjoint(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_outer<float>(a.sim, s);
   if (e != hipSuccess) return device_error(e, "forward simulation launch");
-  e = launch_adjoint(a, s);
+  e = launch_adjoint(a, grad_dev != nullptr, s);
   if (e != hipSuccess) return device_error(e, "adjoint launch");
   return HSIM_OK;
 }

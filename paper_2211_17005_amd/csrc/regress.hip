@@ -288,6 +288,28 @@ __device__ void backprop_layer(const Smem<U, H>& S, int l) {
   }
 }
 
+// out[u] += sum_r w[r] X[r][u] (w = 1 if null) over the R rows of a chunk: every thread sums a
+// slice of rows of one column, the slices are combined in a fixed order.  Ends with a barrier
+// only through the caller's next synchronisation; uses the reduction scratch.
+template <int U, int H>
+__device__ void column_sums(const Smem<U, H>& S, const __bf16* X, const float* w, float* out) {
+  constexpr int R = kMlpRows, P = kMlpThreads / U, RP = R / P;
+  float* part = (float*)S.red();
+  const int tid = opaque_tid(), u = tid % U, p = tid / U;
+  float acc = 0.0f;
+#pragma unroll
+  for (int r = p * RP; r < (p + 1) * RP; ++r) acc += (w ? w[r] : 1.0f) * (float)X[r * S.SW + u];
+  part[p * U + u] = acc;
+  __syncthreads();
+  if (tid < U) {
+    float sum = out[tid];
+#pragma unroll
+    for (int q = 0; q < P; ++q) sum += part[q * U + tid];
+    out[tid] = sum;
+  }
+  __syncthreads();
+}
+
 // Gradients of one chunk, accumulated over the batch.
 template <int U, int H>
 __device__ void backward(const Smem<U, H>& S, int n, int pos, float inv_batch, f32x4* accW) {
@@ -301,24 +323,19 @@ __device__ void backward(const Smem<U, H>& S, int n, int pos, float inv_batch, f
     S.dff()[r] = pos ? (f > 0.0f ? dp : 0.0f) : dp;
   }
   __syncthreads();
-  if (opaque_tid() == 0) {
-    float gm = 0.0f, gb = 0.0f;
-    for (int r = 0; r < R; ++r) {
-      gm += S.dpred()[r];
-      gb += S.dff()[r];
+  if (opaque_tid() < 64) {                       // wave 0: fixed-order butterfly over the rows
+    float gm = S.dpred()[opaque_tid()], gb = S.dff()[opaque_tid()];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      gm += __shfl_xor(gm, m);
+      gb += __shfl_xor(gb, m);
     }
-    S.scal()[3] += gm;
-    S.scal()[2] += gb;
-  }
-  {
-    const __bf16* Hh = S.A(H);
-    for (int u = opaque_tid(); u < U; u += kMlpThreads) {
-      float s = 0.0f;
-      for (int r = 0; r < R; ++r) s += S.dff()[r] * (float)Hh[r * S.SW + u];
-      S.gwout()[u] += s;
+    if (opaque_tid() == 0) {
+      S.scal()[3] += gm;
+      S.scal()[2] += gb;
     }
   }
-  __syncthreads();
+  column_sums<U, H>(S, S.A(H), S.dff(), S.gwout());
   {
     __bf16* Hh = S.A(H);
     for (int e = opaque_tid(); e < R * U; e += kMlpThreads) {
@@ -330,14 +347,7 @@ __device__ void backward(const Smem<U, H>& S, int n, int pos, float inv_batch, f
   __syncthreads();
   for (int l = H; l >= 1; --l) {
     accumulate_dw<U, H>(S, l, accW);
-    {
-      const __bf16* dZ = S.A(l);
-      for (int u = opaque_tid(); u < U; u += kMlpThreads) {
-        float s = 0.0f;
-        for (int r = 0; r < R; ++r) s += (float)dZ[r * S.SW + u];
-        S.gbias(l)[u] += s;
-      }
-    }
+    column_sums<U, H>(S, S.A(l), nullptr, S.gbias(l));
     if (l > 1) backprop_layer<U, H>(S, l);
     __syncthreads();
   }

@@ -426,11 +426,11 @@ class Adjoint:
         self.cva0 = torch.empty(1, dtype=torch.float64, device="cuda")
         self.grad = torch.empty(self.P, dtype=torch.float64, device="cuda")
 
-    def __call__(self, market=None, path_begin: int = 0):
+    def __call__(self, market=None, path_begin: int = 0, with_grad: bool = True):
         km = market_struct(self.w.market if market is None else market)
         check(lib().cva_adjoint(ctypes.byref(km.struct), ctypes.byref(self.kp.struct), ctypes.byref(self.g),
-                                self.w.seed, path_begin, self.M, _dptr(self.cva0), _dptr(self.grad),
-                                _dptr(self.ws), self.wsb, _stream()))
+                                self.w.seed, path_begin, self.M, _dptr(self.cva0),
+                                _dptr(self.grad if with_grad else None), _dptr(self.ws), self.wsb, _stream()))
         return self.cva0, self.grad
 
 
