@@ -3,10 +3,15 @@
 //
 // One workgroup (8 waves) trains the network of one pricing date; a persistent grid pulls
 // dates from an atomic work counter, so every date of a regression set trains in one launch.
-// Inside a workgroup a batch is processed in chunks of 64 rows staged in LDS:
+// Inside a workgroup a batch is processed in chunks of 64 rows staged in LDS, every matrix kept
+// row-major ([row][feature], weights [out][in]):
 //   forward   Z_l^T = W_l A_{l-1}^T         (MFMA 16x16x32 BF16, FP32 accumulation)
 //   backward  dW_l += dZ_l^T A_{l-1}        (accumulated in registers over the whole batch)
 //             dH_{l-1}^T = W_l^T dZ_l^T     (masked by the ReLU of layer l-1, in place)
+// Operands whose contraction runs down a column (dZ_l^T, A_{l-1} and W_l^T above) are read
+// with the LDS transpose load of gfx950, so no matrix is stored twice and no operand is
+// gathered element by element.  Each wave computes a block of output tiles so that every
+// fragment it reads feeds several MFMAs.
 // Weights and activations are BF16; accumulators, master weights, Adam moments, the output
 // layer, the loss and the refit are FP32 (FP64 for the refit solve).  All reductions run in a
 // fixed order, so results are bitwise reproducible.
@@ -24,6 +29,7 @@
 namespace hsim {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Thread index hidden from loop-invariant code motion: address arithmetic derived from it is
@@ -36,6 +42,87 @@ __device__ __forceinline__ int opaque_tid() {
 
 __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// LDS transpose load: inside each group of 16 lanes, lane 4t + q supplies the address of four
+// consecutive 16-bit elements, and lane i of the group receives element i % 4 of lane
+// 4t + i / 4 as its element t (t, q = 0..3).
+__device__ __forceinline__ bf16x4 lds_read_tr(const __bf16* p) {
+  typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+  return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)p);
+}
+
+// Element (row, col) of a row-major LDS matrix.  The 16-byte granules of a row are swizzled (granule
+// index XOR bit 2 of the row) and rows are padded to 32 bytes modulo 128, so that the 16-byte row
+// reads of eight consecutive rows and the transpose loads of four consecutive rows both spread
+// over distinct banks.
+__device__ __forceinline__ int lidx(int row, int col, int stride) {
+  return row * stride + (col ^ (((row >> 2) & 1) << 3));
+}
+
+// Per-lane element offsets of the operand reads and tile writes of one swizzled LDS matrix of
+// stride S.  Fragments start at row0 % 16 == 0 (row reads) or row0 % 8 == 0 (column reads) and at
+// col0 % 16 == 0, so the swizzle of every address a lane touches is fixed by the lane: each read
+// is one instruction at a constant offset from these.
+struct LaneOffsets {
+  int rows, cols_lo, cols_hi, tile;
+  __device__ __forceinline__ explicit LaneOffsets(int S) {
+    const int lane = (int)((unsigned)opaque_tid() & 63u), i = lane & 15, g = lane >> 4, s = ((i >> 2) & 1) << 3;
+    rows = i * S + ((8 * g) ^ s);
+    cols_lo = (8 * g + i / 4) * S + 4 * (i % 4);
+    cols_hi = (8 * g + i / 4 + 4) * S + ((4 * (i % 4)) ^ 8);
+    tile = i * S + ((4 * g) ^ s);
+  }
+};
+
+// The offsets of a thread for the two row strides of the workgroup (inputs / first layer and
+// hidden layers), built once and kept in registers through the training loops.
+struct Lanes {
+  LaneOffsets o0, o;
+  __device__ __forceinline__ Lanes(int S0, int S) : o0(S0), o(S) {}
+  __device__ __forceinline__ const LaneOffsets& of(int S, int S0) const { return S == S0 ? o0 : o; }
+};
+
+// Wave index of the thread, wave-uniform (scalar register).
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Lane permutations of the data-parallel primitives (row = 16 lanes): swap neighbours, swap pairs,
+// mirror inside each half row, mirror inside each row.
+#define HSIM_DPP(v, ctrl) __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false))
+
+// Sum of v over the 64 lanes of the wave in a fixed order, returned in every lane.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += HSIM_DPP(v, 0xB1);               // quad_perm (1, 0, 3, 2)
+  v += HSIM_DPP(v, 0x4E);               // quad_perm (2, 3, 0, 1)
+  v += HSIM_DPP(v, 0x141);              // half-row mirror
+  v += HSIM_DPP(v, 0x140);              // row mirror
+  return (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
+          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32)) +
+          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48)));
+}
+
+// MFMA operand whose eight k values run along a row: lane l receives
+// M[row0 + l % 16][col0 + 8 (l / 16) + t], t = 0..7 (one 16-byte read).
+__device__ __forceinline__ bf16x8 frag_rows(const __bf16* M, const LaneOffsets& o, int S, int row0, int col0) {
+  return *(const bf16x8*)&M[o.rows + row0 * S + col0];
+}
+
+// MFMA operand whose eight k values run down a column: lane l receives
+// M[row0 + 8 (l / 16) + t][col0 + l % 16], t = 0..7 (two transpose loads of four rows each).
+__device__ __forceinline__ bf16x8 frag_cols(const __bf16* M, const LaneOffsets& o, int S, int row0, int col0) {
+  const bf16x4 lo = lds_read_tr(M + o.cols_lo + row0 * S + col0);
+  const bf16x4 hi = lds_read_tr(M + o.cols_hi + row0 * S + col0);
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// The 4 x 1 strip of a 16 x 16 MFMA result tile held by a lane: rows 16 rt + l % 16,
+// columns 16 ot + 4 (l / 16) .. + 3 (four consecutive elements, one 8-byte access).
+__device__ __forceinline__ bf16x4* tile_strip(__bf16* M, const LaneOffsets& o, int S, int rt, int ot) {
+  return (bf16x4*)&M[o.tile + 16 * rt * S + 16 * ot];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -91,14 +178,15 @@ __global__ __launch_bounds__(256) void mlp_stats_kernel(const MlpArgs a) {
 template <int U, int H>
 struct Smem {
   static constexpr int D = kMlpDin, R = kMlpRows;
-  static constexpr int SW0 = D + 8;            // padded row strides (bf16 elements)
-  static constexpr int SW = U + 8;
-  static constexpr int NT = U / 16;
+  static constexpr int SW0 = D + 16;           // padded row strides (bf16 elements)
+  static constexpr int SW = U + 16;
   static constexpr int w_bytes = (U * SW0 + (H - 1) * U * SW) * (int)sizeof(__bf16);
   static constexpr int a_bytes = (R * SW0 + H * R * SW) * (int)sizeof(__bf16);
   static constexpr int f_count = 2 * H * U + 2 * U + 4 * R + 2 * D + 8;
-  static constexpr int red_bytes = kMlpThreads * 8;
+  static constexpr int red_bytes = kMlpThreads * 16;
   static constexpr int bytes = w_bytes + a_bytes + f_count * 4 + red_bytes;
+  static_assert(bytes <= 160 * 1024, "LDS of one workgroup");
+  static_assert(w_bytes % 16 == 0 && a_bytes % 16 == 0 && (f_count * 4) % 16 == 0, "16-byte sections");
 
   __bf16* base;
   __device__ __bf16* W(int l) const {          // l = 1..H : [U][K_l + 8]
@@ -120,9 +208,41 @@ struct Smem {
   __device__ float* xmean() const { return dff() + R; }
   __device__ float* xinv() const { return xmean() + D; }
   __device__ float* scal() const { return xinv() + D; }   // [0] bout [1] mu [2] gbout [3] gmu [4] yscale
-  __device__ double* red() const { return (double*)((char*)base + w_bytes + a_bytes + f_count * 4); }
+  __device__ char* red() const { return (char*)base + w_bytes + a_bytes + f_count * 4; }
+  __device__ float* fpart() const { return (float*)red(); }   // [U/16/BO][R] output partials
   static constexpr int ldk(int l) { return l == 1 ? D : U; }
   static constexpr int lds(int l) { return l == 1 ? SW0 : SW; }
+};
+
+// Output tiles (16 x 16) of a forward or backprop layer, U/16 by 4 per chunk: each wave owns a
+// block of BO x BR of them, waves laid out out-block fastest.
+template <int U>
+struct Blk {
+  static constexpr int NT = U / 16, RT = kMlpRows / 16;
+  static constexpr int BO = U >= 64 ? 2 : 1;
+  static constexpr int BR = U >= 128 ? 2 : 1;
+  static constexpr int NOB = NT / BO;
+  static_assert(NOB * (RT / BR) == kMlpWaves, "one block per wave");
+};
+
+// Weight-gradient tiles of layer L (U/16 out tiles by K_L/16 in tiles), held in registers over a
+// batch: each wave owns a block of BO x BI of them (in block fastest); with fewer tiles than
+// waves the remaining waves own none.
+constexpr int dw_kt(int U, int L) { return (L == 1 ? kMlpDin : U) / 16; }
+constexpr int dw_tw(int U, int L) {
+  return (U / 16) * dw_kt(U, L) >= kMlpWaves ? (U / 16) * dw_kt(U, L) / kMlpWaves : 1;
+}
+constexpr int dw_base(int U, int L) { return L == 1 ? 0 : dw_tw(U, 1) + (L - 2) * dw_tw(U, 2); }
+constexpr int dw_slots(int U, int H) { return dw_tw(U, 1) + (H - 1) * dw_tw(U, 2); }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+template <int U, int L>
+struct DwMap {
+  static constexpr int NT = U / 16, KT = dw_kt(U, L), TW = dw_tw(U, L);
+  static constexpr int BI = cmin(cmin(KT, TW), 4);
+  static constexpr int BO = TW / BI;
+  static constexpr int NIB = KT / BI, NOB = NT / BO;
+  static_assert(BO * BI == TW && NIB * NOB * TW == NT * KT && NIB * NOB <= kMlpWaves, "tiling");
 };
 
 // Copy the FP32 parameters of one network into the workgroup's BF16 / FP32 LDS copies.
@@ -132,7 +252,7 @@ __device__ void load_weights(const Smem<U, H>& S, const float* P, const MlpLayou
     const int K = S.ldk(l), SWl = S.lds(l);
     __bf16* W = S.W(l);
     const float* src = P + L.w_off(l);
-    for (int e = opaque_tid(); e < U * K; e += kMlpThreads) W[(e / K) * SWl + e % K] = (__bf16)src[e];
+    for (int e = opaque_tid(); e < U * K; e += kMlpThreads) W[lidx(e / K, e % K, SWl)] = (__bf16)src[e];
     for (int e = opaque_tid(); e < U; e += kMlpThreads) S.bias(l)[e] = P[L.b_off(l) + e];
   }
   for (int e = opaque_tid(); e < U; e += kMlpThreads) S.wout()[e] = P[L.wout_off() + e];
@@ -142,217 +262,297 @@ __device__ void load_weights(const Smem<U, H>& S, const float* P, const MlpLayou
   }
 }
 
-// Stage rows [r0, r0 + n) of one date: standardised inputs (BF16) and scaled targets.
-template <int U, int H>
-__device__ void load_chunk(const Smem<U, H>& S, const MlpArgs& a, int date, int64_t r0, int n) {
-  constexpr int R = kMlpRows, D = kMlpDin;
-  __bf16* A0 = S.A(0);
-  for (int e = opaque_tid(); e < R * D; e += kMlpThreads) {
-    const int r = e % R, f = e / R;
-    float v = 0.0f;
-    if (f < a.d_in && r < n)
-      v = (a.X[((int64_t)date * a.n_feat + f) * a.M + r0 + r] - S.xmean()[f]) * S.xinv()[f];
-    A0[r * S.SW0 + f] = (__bf16)v;
-  }
-  if (a.Y != nullptr && opaque_tid() < R) {     // prediction has no targets
-    const int r = opaque_tid();
-    S.ybuf()[r] = r < n ? a.Y[(int64_t)date * a.M + r0 + r] / S.scal()[4] : 0.0f;
-  }
-}
+// ------------------------------------------------------------------------------------------
+// chunk staging: global -> registers (issued one chunk ahead) -> LDS
+// ------------------------------------------------------------------------------------------
+static_assert(kMlpThreads == kMlpRows * (kMlpDin / 4), "one feature quad of one row per thread");
 
-// Forward through the hidden layers (BF16 activations left in A(1..H)) and the output layer
-// (FP32, into fbuf).
-template <int U, int H>
-__device__ void forward(const Smem<U, H>& S) {
-  constexpr int R = kMlpRows, NT = U / 16, RT = R / 16;
-  const int tid = opaque_tid(), wave = tid / 64, lane = tid % 64;
-  const int li = lane % 16, lk = 8 * (lane / 16);
-  for (int l = 1; l <= H; ++l) {
-    const int K = S.ldk(l), SWl = S.lds(l);
-    const __bf16* W = S.W(l);
-    const __bf16* Ain = S.A(l - 1);
-    __bf16* Aout = S.A(l);
-    const float* b = S.bias(l);
-#pragma unroll 1
-    for (int j = wave; j < NT * RT; j += kMlpWaves) {
-      const int ot = j / RT, rt = j % RT;
-      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      for (int k0 = 0; k0 < K; k0 += 32) {
-        const bf16x8 av = *(const bf16x8*)&W[(16 * ot + li) * SWl + k0 + lk];
-        const bf16x8 bv = *(const bf16x8*)&Ain[(16 * rt + li) * SWl + k0 + lk];
-        acc = mfma16(av, bv, acc);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int out = 16 * ot + 4 * (lane / 16) + v, r = 16 * rt + li;
-        const float h = acc[v] + b[out];
-        Aout[r * S.SW + out] = (__bf16)(h > 0.0f ? h : 0.0f);
-      }
-    }
-    __syncthreads();
-  }
-  // output layer: 8 threads per row, fixed-order butterfly of the partial sums
-  {
-    const int r = opaque_tid() / 8, qd = opaque_tid() % 8;
-    const __bf16* Hh = S.A(H) + r * S.SW;
-    float s = 0.0f;
-    for (int u = qd * (U / 8); u < (qd + 1) * (U / 8); ++u) s += (float)Hh[u] * S.wout()[u];
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 4);
-    if (qd == 0) S.fbuf()[r] = s + S.scal()[0];
-  }
-  __syncthreads();
-}
-
-template <int U, int H>
-struct Tiles {
-  static constexpr int NT = U / 16;
-  static constexpr int T1 = NT * (kMlpDin / 16);
-  static constexpr int TL = NT * NT;
-  static constexpr int total = T1 + (H - 1) * TL;
-  static constexpr int slots = (total + kMlpWaves - 1) / kMlpWaves;
-  __device__ static int base(int l) { return l == 1 ? 0 : T1 + (l - 2) * TL; }
-  __device__ static int count(int l) { return l == 1 ? T1 : TL; }
+struct ChunkRegs {
+  float x[4];                   // features 4 (t / 64) .. + 3 of row t % 64
+  float y;                      // target of row t (threads t < 64)
 };
 
-// dW_l += dZ_l^T A_{l-1} for the tiles this wave owns (tile g: wave g % waves, slot g / waves).
+// Per-thread source of the chunk staging for one date, set up once: thread t loads features
+// f0 .. f0 + 3 (f0 = 4 (t / 64)) of row t % 64 and, for t < 64, the target of row t.
+struct Feeder {
+  const float* x;
+  const float* y;
+  int64_t M;
+  int nf, r;
+  __device__ __forceinline__ Feeder(const MlpArgs& a, int date) {
+    const int t = opaque_tid(), f0 = 4 * (t / kMlpRows);
+    r = t % kMlpRows;
+    x = a.X + ((int64_t)date * a.n_feat + f0) * a.M + r;
+    y = (a.Y != nullptr && t < kMlpRows) ? a.Y + (int64_t)date * a.M + t : nullptr;
+    M = a.M;
+    nf = max(0, min(4, a.d_in - f0));
+  }
+  // rows [r0, r0 + n) (zero beyond the sample and beyond d_in)
+  __device__ __forceinline__ ChunkRegs load(int64_t r0, int n) const {
+    ChunkRegs c;
+    const bool row_ok = r < n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c.x[q] = (row_ok && q < nf) ? x[q * M + r0] : 0.0f;
+    c.y = (y != nullptr && row_ok) ? y[r0] : 0.0f;
+    return c;
+  }
+};
+
+// Standardised inputs (BF16) into A(0); returns the scaled target of row t held by thread t < 64
+// (and stores it in ybuf for the refit).
 template <int U, int H>
-__device__ void accumulate_dw(const Smem<U, H>& S, int l, f32x4* accW) {
-  using TT = Tiles<U, H>;
-  const int tid = opaque_tid(), wave = tid / 64, lane = tid % 64;
-  const int li = lane % 16, lk = 8 * (lane / 16);
-  const int K = S.ldk(l), SWin = S.lds(l), KT = K / 16;
-  const __bf16* dZ = S.A(l);
-  const __bf16* Ain = S.A(l - 1);
-  const int b = TT::base(l), c = TT::count(l);
+__device__ __forceinline__ float store_chunk(const Smem<U, H>& S, const ChunkRegs& c, int n) {
+  const int t = opaque_tid(), r = t % kMlpRows, f0 = 4 * (t / kMlpRows);
+  const f32x4 mean = *(const f32x4*)&S.xmean()[f0];
+  const f32x4 inv = *(const f32x4*)&S.xinv()[f0];
+  bf16x4 v;
 #pragma unroll
-  for (int s = 0; s < TT::slots; ++s) {
-    const int g = kMlpWaves * s + wave;
-    if (g < b || g >= b + c) continue;
-    const int ot = (g - b) / KT, it = (g - b) % KT;
-    f32x4 acc = accW[s];
+  for (int q = 0; q < 4; ++q) v[q] = (__bf16)(r < n ? (c.x[q] - mean[q]) * inv[q] : 0.0f);
+  *(bf16x4*)&S.A(0)[lidx(r, f0, S.SW0)] = v;
+  float y = 0.0f;
+  if (t < kMlpRows) {
+    y = t < n ? c.y / S.scal()[4] : 0.0f;
+    S.ybuf()[t] = y;
+  }
+  return y;
+}
+
+// ------------------------------------------------------------------------------------------
+// forward
+// ------------------------------------------------------------------------------------------
+// Hidden layer L: A_L = relu(W_L A_{L-1} + b_L), BF16 into A(L).
+template <int U, int H, int L>
+__device__ void forward_layer(const Smem<U, H>& S, const Lanes& ln) {
+  using B = Blk<U>;
+  constexpr int K = Smem<U, H>::ldk(L), SWl = Smem<U, H>::lds(L);
+  constexpr int SW = Smem<U, H>::SW;
+  const int wave = wave_id(), lane = lane_id();
+  const int ob = wave % B::NOB, rb = wave / B::NOB;
+  const LaneOffsets& oi = L == 1 ? ln.o0 : ln.o;
+  const LaneOffsets& oo = ln.o;
+  const __bf16* W = S.W(L);
+  const __bf16* Ain = S.A(L - 1);
+  __bf16* Aout = S.A(L);
+  f32x4 acc[B::BO][B::BR];
 #pragma unroll
-    for (int k0 = 0; k0 < kMlpRows; k0 += 32) {
-      bf16x8 av, bv;
+  for (int x = 0; x < B::BO; ++x)
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        av[t] = dZ[(k0 + lk + t) * S.SW + 16 * ot + li];
-        bv[t] = Ain[(k0 + lk + t) * SWin + 16 * it + li];
+    for (int y = 0; y < B::BR; ++y) acc[x][y] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 av[B::BO], bv[B::BR];
+#pragma unroll
+    for (int x = 0; x < B::BO; ++x) av[x] = frag_rows(W, oi, SWl, 16 * (ob * B::BO + x), k0);
+#pragma unroll
+    for (int y = 0; y < B::BR; ++y) bv[y] = frag_rows(Ain, oi, SWl, 16 * (rb * B::BR + y), k0);
+#pragma unroll
+    for (int x = 0; x < B::BO; ++x)
+#pragma unroll
+      for (int y = 0; y < B::BR; ++y) acc[x][y] = mfma16(av[x], bv[y], acc[x][y]);
+  }
+  const float* b = S.bias(L);
+  float pf[B::BR];                      // last layer: this lane's part of f = A_H w_out
+#pragma unroll
+  for (int y = 0; y < B::BR; ++y) pf[y] = 0.0f;
+#pragma unroll
+  for (int x = 0; x < B::BO; ++x) {
+    const int out0 = 16 * (ob * B::BO + x) + 4 * (lane / 16);
+    const f32x4 bb = *(const f32x4*)&b[out0];
+    f32x4 wo = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (L == H) wo = *(const f32x4*)&S.wout()[out0];
+#pragma unroll
+    for (int y = 0; y < B::BR; ++y) {
+      bf16x4 h;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        h[v] = (__bf16)fmaxf(acc[x][y][v] + bb[v], 0.0f);
+        if constexpr (L == H) pf[y] += (float)h[v] * wo[v];
       }
-      acc = mfma16(av, bv, acc);
-    }
-    accW[s] = acc;
-    asm volatile("" ::: "memory");      // keep the gathers of one tile together
-  }
-}
-
-// dH_{l-1} = dZ_l W_l masked by the ReLU of layer l-1, written over A(l-1) (l >= 2).
-template <int U, int H>
-__device__ void backprop_layer(const Smem<U, H>& S, int l) {
-  constexpr int R = kMlpRows, NT = U / 16, RT = R / 16, NJ = (NT * RT + kMlpWaves - 1) / kMlpWaves;
-  const int tid = opaque_tid(), wave = tid / 64, lane = tid % 64;
-  const int li = lane % 16, lk = 8 * (lane / 16);
-  const __bf16* W = S.W(l);
-  const __bf16* dZ = S.A(l);
-  __bf16* Aprev = S.A(l - 1);
-  f32x4 dh[NJ];
-#pragma unroll
-  for (int m = 0; m < NJ; ++m) {
-    const int j = wave + kMlpWaves * m, it = j / RT, rt = j % RT;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (j >= NT * RT) {
-      dh[m] = acc;
-      continue;
-    }
-    for (int k0 = 0; k0 < U; k0 += 32) {
-      bf16x8 av;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) av[t] = W[(k0 + lk + t) * S.SW + 16 * it + li];
-      const bf16x8 bv = *(const bf16x8*)&dZ[(16 * rt + li) * S.SW + k0 + lk];
-      acc = mfma16(av, bv, acc);
-    }
-    dh[m] = acc;
-  }
-  __syncthreads();                      // every read of A(l-1) and dZ_l is done
-#pragma unroll
-  for (int m = 0; m < NJ; ++m) {
-    const int j = wave + kMlpWaves * m, it = j / RT, rt = j % RT;
-    if (j >= NT * RT) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int in = 16 * it + 4 * (lane / 16) + v, r = 16 * rt + li;
-      __bf16* p = &Aprev[r * S.SW + in];
-      *p = (float)*p > 0.0f ? (__bf16)dh[m][v] : (__bf16)0.0f;
+      *tile_strip(Aout, oo, SW, rb * B::BR + y, ob * B::BO + x) = h;
     }
   }
-}
-
-// out[u] += sum_r w[r] X[r][u] (w = 1 if null) over the R rows of a chunk: every thread sums a
-// slice of rows of one column, the slices are combined in a fixed order.  Ends with a barrier
-// only through the caller's next synchronisation; uses the reduction scratch.
-template <int U, int H>
-__device__ void column_sums(const Smem<U, H>& S, const __bf16* X, const float* w, float* out) {
-  constexpr int R = kMlpRows, P = kMlpThreads / U, RP = R / P;
-  float* part = (float*)S.red();
-  const int tid = opaque_tid(), u = tid % U, p = tid / U;
-  float acc = 0.0f;
+  if constexpr (L == H) {
+    // the four lane groups hold the same rows: fold them, then one partial per out block and row
 #pragma unroll
-  for (int r = p * RP; r < (p + 1) * RP; ++r) acc += (w ? w[r] : 1.0f) * (float)X[r * S.SW + u];
-  part[p * U + u] = acc;
-  __syncthreads();
-  if (tid < U) {
-    float sum = out[tid];
-#pragma unroll
-    for (int q = 0; q < P; ++q) sum += part[q * U + tid];
-    out[tid] = sum;
+    for (int y = 0; y < B::BR; ++y) {
+      pf[y] += __shfl_xor(pf[y], 16);
+      pf[y] += __shfl_xor(pf[y], 32);
+      if (lane < 16) S.fpart()[ob * kMlpRows + 16 * (rb * B::BR + y) + lane] = pf[y];
+    }
   }
   __syncthreads();
 }
 
-// Gradients of one chunk, accumulated over the batch.
+// f of row r (after the forward): the out-block partials in a fixed order, plus b_out.
 template <int U, int H>
-__device__ void backward(const Smem<U, H>& S, int n, int pos, float inv_batch, f32x4* accW) {
-  constexpr int R = kMlpRows;
-  if (opaque_tid() < R) {
-    const int r = opaque_tid();
-    const float f = S.fbuf()[r];
-    const float pred = (pos ? (f > 0.0f ? f : 0.0f) : f) + S.scal()[1];
-    const float dp = r < n ? 2.0f * (pred - S.ybuf()[r]) * inv_batch : 0.0f;
-    S.dpred()[r] = dp;
-    S.dff()[r] = pos ? (f > 0.0f ? dp : 0.0f) : dp;
-  }
-  __syncthreads();
-  if (opaque_tid() < 64) {                       // wave 0: fixed-order butterfly over the rows
-    float gm = S.dpred()[opaque_tid()], gb = S.dff()[opaque_tid()];
+__device__ __forceinline__ float output_of_row(const Smem<U, H>& S, int r) {
+  float f = 0.0f;
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      gm += __shfl_xor(gm, m);
-      gb += __shfl_xor(gb, m);
-    }
-    if (opaque_tid() == 0) {
-      S.scal()[3] += gm;
-      S.scal()[2] += gb;
+  for (int q = 0; q < Blk<U>::NOB; ++q) f += S.fpart()[q * kMlpRows + r];
+  return f + S.scal()[0];
+}
+
+template <int U, int H>
+__device__ void forward(const Smem<U, H>& S, const Lanes& ln) {
+  forward_layer<U, H, 1>(S, ln);
+  if constexpr (H >= 2) forward_layer<U, H, 2>(S, ln);
+  if constexpr (H >= 3) forward_layer<U, H, 3>(S, ln);
+}
+
+// ------------------------------------------------------------------------------------------
+// backward
+// ------------------------------------------------------------------------------------------
+// dW_L += dZ_L^T A_{L-1} over the chunk for the tiles this wave owns, and the bias gradient of
+// its out tiles (dZ_L^T times a ones column, in the waves owning in block 0).
+template <int U, int H, int L>
+__device__ void accumulate_dw(const Smem<U, H>& S, const Lanes& ln, f32x4* accW) {
+  using M = DwMap<U, L>;
+  const int wave = wave_id(), lane = lane_id();
+  const int ib = wave % M::NIB, ob = wave / M::NIB;
+  if (ob >= M::NOB) return;
+  const __bf16* dZ = S.A(L);
+  const __bf16* Ain = S.A(L - 1);
+  constexpr int SW = Smem<U, H>::SW, SWin = Smem<U, H>::lds(L);
+  const LaneOffsets& oz = ln.o;
+  const LaneOffsets& oi = L == 1 ? ln.o0 : ln.o;
+  f32x4* acc = accW + dw_base(U, L);
+  f32x4 gb[M::BO];
+#pragma unroll
+  for (int x = 0; x < M::BO; ++x) gb[x] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  bf16x8 ones;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) ones[t] = (__bf16)1.0f;
+#pragma unroll
+  for (int k0 = 0; k0 < kMlpRows; k0 += 32) {
+    bf16x8 av[M::BO], bv[M::BI];
+#pragma unroll
+    for (int x = 0; x < M::BO; ++x) av[x] = frag_cols(dZ, oz, SW, k0, 16 * (ob * M::BO + x));
+#pragma unroll
+    for (int y = 0; y < M::BI; ++y) bv[y] = frag_cols(Ain, oi, SWin, k0, 16 * (ib * M::BI + y));
+#pragma unroll
+    for (int x = 0; x < M::BO; ++x)
+#pragma unroll
+      for (int y = 0; y < M::BI; ++y) acc[x * M::BI + y] = mfma16(av[x], bv[y], acc[x * M::BI + y]);
+    if (ib == 0) {
+#pragma unroll
+      for (int x = 0; x < M::BO; ++x) gb[x] = mfma16(av[x], ones, gb[x]);
     }
   }
-  column_sums<U, H>(S, S.A(H), S.dff(), S.gwout());
-  {
-    __bf16* Hh = S.A(H);
-    for (int e = opaque_tid(); e < R * U; e += kMlpThreads) {
-      const int r = e / U, u = e % U;
-      __bf16* p = &Hh[r * S.SW + u];
-      *p = (float)*p > 0.0f ? (__bf16)(S.dff()[r] * S.wout()[u]) : (__bf16)0.0f;
-    }
+  if (ib == 0 && lane % 16 == 0) {
+#pragma unroll
+    for (int x = 0; x < M::BO; ++x)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S.gbias(L)[16 * (ob * M::BO + x) + 4 * (lane / 16) + v] += gb[x][v];
   }
-  __syncthreads();
-  for (int l = H; l >= 1; --l) {
-    accumulate_dw<U, H>(S, l, accW);
-    column_sums<U, H>(S, S.A(l), nullptr, S.gbias(l));
-    if (l > 1) backprop_layer<U, H>(S, l);
+}
+
+// dH_{L-1}^T = W_L^T dZ_L^T for the tiles this wave owns (L >= 2).
+template <int U, int H, int L>
+__device__ void backprop_compute(const Smem<U, H>& S, const Lanes& ln, f32x4 (&dh)[Blk<U>::BO][Blk<U>::BR]) {
+  using B = Blk<U>;
+  constexpr int SW = Smem<U, H>::SW;
+  const int wave = wave_id();
+  const int ob = wave % B::NOB, rb = wave / B::NOB;
+  const LaneOffsets& o = ln.o;
+  const __bf16* W = S.W(L);
+  const __bf16* dZ = S.A(L);
+#pragma unroll
+  for (int x = 0; x < B::BO; ++x)
+#pragma unroll
+    for (int y = 0; y < B::BR; ++y) dh[x][y] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k0 = 0; k0 < U; k0 += 32) {
+    bf16x8 av[B::BO], bv[B::BR];
+#pragma unroll
+    for (int x = 0; x < B::BO; ++x) av[x] = frag_cols(W, o, SW, k0, 16 * (ob * B::BO + x));
+#pragma unroll
+    for (int y = 0; y < B::BR; ++y) bv[y] = frag_rows(dZ, o, SW, 16 * (rb * B::BR + y), k0);
+#pragma unroll
+    for (int x = 0; x < B::BO; ++x)
+#pragma unroll
+      for (int y = 0; y < B::BR; ++y) dh[x][y] = mfma16(av[x], bv[y], dh[x][y]);
+  }
+}
+
+// dZ_{L-1} = dH_{L-1} masked by the ReLU of layer L-1, written over A(L-1).
+template <int U, int H, int L>
+__device__ void backprop_store(const Smem<U, H>& S, const Lanes& ln, const f32x4 (&dh)[Blk<U>::BO][Blk<U>::BR]) {
+  using B = Blk<U>;
+  constexpr int SW = Smem<U, H>::SW;
+  const int wave = wave_id();
+  const int ob = wave % B::NOB, rb = wave / B::NOB;
+  const LaneOffsets& o = ln.o;
+  __bf16* Ap = S.A(L - 1);
+#pragma unroll
+  for (int x = 0; x < B::BO; ++x)
+#pragma unroll
+    for (int y = 0; y < B::BR; ++y) {
+      bf16x4* p = tile_strip(Ap, o, SW, rb * B::BR + y, ob * B::BO + x);
+      const bf16x4 a = *p;
+      bf16x4 z;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) z[v] = (float)a[v] > 0.0f ? (__bf16)dh[x][y][v] : (__bf16)0.0f;
+      *p = z;
+    }
+}
+
+template <int U, int H, int L>
+__device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, f32x4* accW) {
+  accumulate_dw<U, H, L>(S, ln, accW);
+  if constexpr (L > 1) {
+    f32x4 dh[Blk<U>::BO][Blk<U>::BR];
+    backprop_compute<U, H, L>(S, ln, dh);
+    __syncthreads();                    // every read of A(L-1) and dZ_L is done
+    backprop_store<U, H, L>(S, ln, dh);
+    __syncthreads();
+    layer_backward<U, H, L - 1>(S, ln, accW);
+  } else {
     __syncthreads();
   }
 }
 
+// Gradients of one chunk, accumulated over the batch.  dff of the chunk's rows is in LDS.
+template <int U, int H>
+__device__ void backward(const Smem<U, H>& S, const Lanes& ln, f32x4* accW) {
+  const int tid = opaque_tid();
+  // dZ_H = [A_H > 0] dff w_out^T in place, and the partial sums of dff^T A_H (output weights)
+  {
+    constexpr int UQ = U / 4, RS = kMlpThreads / UQ, RPS = kMlpRows / RS;
+    const int uq = tid % UQ, rs = tid / UQ;
+    const f32x4 wo = *(const f32x4*)&S.wout()[4 * uq];
+    f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < RPS; ++k) {
+      const int r = rs * RPS + k;
+      bf16x4* p = (bf16x4*)&S.A(H)[lidx(r, 4 * uq, Smem<U, H>::SW)];
+      const bf16x4 a = *p;
+      const float d = S.dff()[r];
+      bf16x4 z;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float av = (float)a[q];
+        z[q] = av > 0.0f ? (__bf16)(d * wo[q]) : (__bf16)0.0f;
+        g[q] += d * av;
+      }
+      *p = z;
+    }
+    ((f32x4*)S.red())[rs * UQ + uq] = g;
+  }
+  __syncthreads();
+  if (tid < U) {
+    constexpr int RS = kMlpThreads / (U / 4);
+    const float* part = (const float*)S.red();
+    float s = S.gwout()[tid];
+#pragma unroll
+    for (int q = 0; q < RS; ++q) s += part[q * U + tid];
+    S.gwout()[tid] = s;
+  }
+  layer_backward<U, H, H>(S, ln, accW);
+}
+
+// ------------------------------------------------------------------------------------------
+// Adam
+// ------------------------------------------------------------------------------------------
 struct AdamStep {
   float lr, b1, b2, eps, ic1, ic2;      // ic1 = 1 / (1 - b1^t), ic2 = 1 / (1 - b2^t)
   __device__ float operator()(float p, float g, float* m, float* v) const {
@@ -366,30 +566,40 @@ struct AdamStep {
   }
 };
 
+template <int U, int H, int L>
+__device__ void adam_layer(const Smem<U, H>& S, const MlpLayout& Lay, float* P, float* Mm, float* Vv,
+                           const AdamStep& st, f32x4* accW) {
+  using M = DwMap<U, L>;
+  constexpr int K = L == 1 ? kMlpDin : U, SWl = Smem<U, H>::lds(L);
+  const int wave = wave_id(), lane = lane_id();
+  const int ib = wave % M::NIB, ob = wave / M::NIB;
+  if (ob >= M::NOB) return;
+  f32x4* acc = accW + dw_base(U, L);
+#pragma unroll
+  for (int x = 0; x < M::BO; ++x)
+#pragma unroll
+    for (int y = 0; y < M::BI; ++y) {
+      const int s = x * M::BI + y, ot = ob * M::BO + x, it = ib * M::BI + y;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int out = 16 * ot + 4 * (lane / 16) + v, in = 16 * it + lane % 16;
+        const int idx = Lay.w_off(L) + out * K + in;
+        const float p = st(P[idx], acc[s][v], &Mm[idx], &Vv[idx]);
+        P[idx] = p;
+        S.W(L)[lidx(out, in, SWl)] = (__bf16)p;
+      }
+      acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      asm volatile("" ::: "memory");    // one tile's moments in flight at a time
+    }
+}
+
 template <int U, int H>
 __device__ void adam_update(const Smem<U, H>& S, const MlpLayout& L, float* P, float* Mm, float* Vv,
                             const AdamStep& st, f32x4* accW) {
-  using TT = Tiles<U, H>;
-  const int tid = opaque_tid(), wave = tid / 64, lane = tid % 64;
-  const int li = lane % 16;
-#pragma unroll
-  for (int s = 0; s < TT::slots; ++s) {
-    const int g = kMlpWaves * s + wave;
-    if (g >= TT::total) continue;
-    const int l = g < TT::T1 ? 1 : 2 + (g - TT::T1) / TT::TL;
-    const int b = TT::base(l), K = S.ldk(l), KT = K / 16;
-    const int ot = (g - b) / KT, it = (g - b) % KT;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int out = 16 * ot + 4 * (lane / 16) + v, in = 16 * it + li;
-      const int idx = L.w_off(l) + out * K + in;
-      const float p = st(P[idx], accW[s][v], &Mm[idx], &Vv[idx]);
-      P[idx] = p;
-      S.W(l)[out * S.lds(l) + in] = (__bf16)p;
-    }
-    accW[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    asm volatile("" ::: "memory");      // one tile's moments in flight at a time
-  }
+  adam_layer<U, H, 1>(S, L, P, Mm, Vv, st, accW);
+  if constexpr (H >= 2) adam_layer<U, H, 2>(S, L, P, Mm, Vv, st, accW);
+  if constexpr (H >= 3) adam_layer<U, H, 3>(S, L, P, Mm, Vv, st, accW);
+  static_assert(H <= 3, "up to three hidden layers");
   for (int l = 1; l <= H; ++l)
     for (int u = opaque_tid(); u < U; u += kMlpThreads) {
       const int idx = L.b_off(l) + u;
@@ -420,23 +630,29 @@ __device__ void adam_update(const Smem<U, H>& S, const MlpLayout& L, float* P, f
   __syncthreads();
 }
 
+// ------------------------------------------------------------------------------------------
+// full-sample passes: loss and refit
+// ------------------------------------------------------------------------------------------
 // Full-sample loss with the output ReLU (pos = 1).
 template <int U, int H>
-__device__ float full_loss(const Smem<U, H>& S, const MlpArgs& a, int date) {
+__device__ float full_loss(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, const MlpArgs& a) {
+  constexpr int R = kMlpRows;
   double e = 0.0;
-  for (int64_t r0 = 0; r0 < a.M; r0 += kMlpRows) {
-    const int n = (int)min((int64_t)kMlpRows, a.M - r0);
-    load_chunk<U, H>(S, a, date, r0, n);
+  ChunkRegs c = feed.load(0, (int)min((int64_t)R, a.M));
+  for (int64_t r0 = 0; r0 < a.M; r0 += R) {
+    const int n = (int)min((int64_t)R, a.M - r0);
+    const float y = store_chunk<U, H>(S, c, n);
+    if (r0 + R < a.M) c = feed.load(r0 + R, (int)min((int64_t)R, a.M - r0 - R));
     __syncthreads();
-    forward<U, H>(S);
-    if (opaque_tid() < n) {
-      const float f = S.fbuf()[opaque_tid()];
-      const float d = (f > 0.0f ? f : 0.0f) + S.scal()[1] - S.ybuf()[opaque_tid()];
+    forward<U, H>(S, ln);
+    const int t = opaque_tid();
+    if (t < n) {
+      const float d = fmaxf(output_of_row<U, H>(S, t), 0.0f) + S.scal()[1] - y;
       e += (double)d * (double)d;
     }
-    __syncthreads();
   }
-  double* red = S.red();
+  __syncthreads();
+  double* red = (double*)S.red();
   red[opaque_tid()] = e;
   __syncthreads();
   for (int w = kMlpThreads / 2; w > 0; w >>= 1) {
@@ -450,11 +666,11 @@ __device__ float full_loss(const Smem<U, H>& S, const MlpArgs& a, int date) {
 
 // Least-squares refit of (w_out, b_out) on the frozen hidden features, mu fixed.
 template <int U, int H>
-__device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const MlpLayout& L, float* P,
-                      double* G) {
+__device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, const MlpArgs& a,
+                      const MlpLayout& L, float* P, double* G) {
   constexpr int NT = U / 16, NG = NT * NT, GS = (NG + kMlpWaves - 1) / kMlpWaves, N = U + 1;
-  const int tid = opaque_tid(), wave = tid / 64, lane = tid % 64;
-  const int li = lane % 16, lk = 8 * (lane / 16);
+  constexpr int R = kMlpRows;
+  const int tid = opaque_tid(), wave = wave_id(), lane = lane_id();
   // per-chunk Gram tiles come from the matrix cores in FP32 (exact products of BF16 values,
   // 64-term sums); the sum over chunks is carried in FP64
   double accG[GS][4];
@@ -464,12 +680,19 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
     for (int v = 0; v < 4; ++v) accG[s][v] = 0.0;
   double hs = 0.0, hy = 0.0, ys = 0.0;        // thread u: sum h_u, sum h_u (y - mu); thread U: sum (y - mu)
   const float mu = S.scal()[1];
-  for (int64_t r0 = 0; r0 < a.M; r0 += kMlpRows) {
-    const int n = (int)min((int64_t)kMlpRows, a.M - r0);
-    load_chunk<U, H>(S, a, date, r0, n);
+  ChunkRegs c = feed.load(0, (int)min((int64_t)R, a.M));
+  for (int64_t r0 = 0; r0 < a.M; r0 += R) {
+    const int n = (int)min((int64_t)R, a.M - r0);
+    store_chunk<U, H>(S, c, n);
+    if (r0 + R < a.M) c = feed.load(r0 + R, (int)min((int64_t)R, a.M - r0 - R));
     __syncthreads();
-    forward<U, H>(S);
-    const __bf16* Hh = S.A(H);
+    forward<U, H>(S, ln);
+    __bf16* Hh = S.A(H);
+    const LaneOffsets& oh = ln.o;
+    if (n < R) {                              // rows beyond the sample take no part
+      for (int e = tid; e < (R - n) * U; e += kMlpThreads) Hh[lidx(n + e / U, e % U, Smem<U, H>::SW)] = (__bf16)0.0f;
+      __syncthreads();
+    }
 #pragma unroll
     for (int s = 0; s < GS; ++s) {
       const int g = kMlpWaves * s + wave;
@@ -477,28 +700,19 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
       const int ot = g / NT, it = g % NT;
       f32x4 part = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int k0 = 0; k0 < kMlpRows; k0 += 32) {
-        bf16x8 av, bv;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const bool ok = k0 + lk + t < n;
-          av[t] = ok ? Hh[(k0 + lk + t) * S.SW + 16 * ot + li] : (__bf16)0.0f;
-          bv[t] = ok ? Hh[(k0 + lk + t) * S.SW + 16 * it + li] : (__bf16)0.0f;
-        }
-        part = mfma16(av, bv, part);
-      }
+      for (int k0 = 0; k0 < R; k0 += 32)
+        part = mfma16(frag_cols(Hh, oh, Smem<U, H>::SW, k0, 16 * ot), frag_cols(Hh, oh, Smem<U, H>::SW, k0, 16 * it), part);
 #pragma unroll
       for (int v = 0; v < 4; ++v) accG[s][v] += (double)part[v];
     }
-    if (opaque_tid() < U) {
-      const int u = opaque_tid();
+    if (tid < U) {
 #pragma unroll 1
       for (int r = 0; r < n; ++r) {
-        const double h = (float)Hh[r * S.SW + u];
+        const double h = (float)Hh[lidx(r, tid, Smem<U, H>::SW)];
         hs += h;
         hy += h * (double)(S.ybuf()[r] - mu);
       }
-    } else if (opaque_tid() == U) {
+    } else if (tid == U) {
       for (int r = 0; r < n; ++r) ys += (double)(S.ybuf()[r] - mu);
     }
     __syncthreads();
@@ -510,14 +724,14 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
     if (g >= NG) continue;
     const int ot = g / NT, it = g % NT;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) G[(16 * ot + 4 * (lane / 16) + v) * N + 16 * it + li] = accG[s][v];
+    for (int v = 0; v < 4; ++v) G[(16 * ot + 4 * (lane / 16) + v) * N + 16 * it + lane % 16] = accG[s][v];
   }
   double* rhs = G + N * N;
-  if (opaque_tid() < U) {
-    G[opaque_tid() * N + U] = hs;
-    G[U * N + opaque_tid()] = hs;
-    rhs[opaque_tid()] = hy;
-  } else if (opaque_tid() == U) {
+  if (tid < U) {
+    G[tid * N + U] = hs;
+    G[U * N + tid] = hs;
+    rhs[tid] = hy;
+  } else if (tid == U) {
     G[U * N + U] = (double)a.M;
     rhs[U] = ys;
   }
@@ -525,7 +739,7 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
   __syncthreads();
   // ridge of kRefitRidge times the mean diagonal: keeps dead units (zero columns) at weight 0 and
   // bounds the conditioning of the normal equations
-  if (opaque_tid() == 0) {
+  if (tid == 0) {
     double tr = 0.0;
 #pragma unroll 1
     for (int i = 0; i < N; ++i) tr += G[i * N + i];
@@ -584,9 +798,12 @@ __device__ void refit(const Smem<U, H>& S, const MlpArgs& a, int date, const Mlp
   __syncthreads();
 }
 
+// ------------------------------------------------------------------------------------------
+// BaseAlg for one date
+// ------------------------------------------------------------------------------------------
 template <int U, int H>
 __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
-  using TT = Tiles<U, H>;
+  constexpr int R = kMlpRows;
   const MlpLayout L{U, H};
   const int date = a.dates[job];
   const int NP = L.n_params();
@@ -606,7 +823,6 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
     const int rows = l <= H ? U : 1;
     const int stride = l == 1 ? kMlpDin : U;
     const int off = l <= H ? L.w_off(l) : L.wout_off();
-    const float bound = rsqrtf((float)fan_in);
     for (int e = opaque_tid(); e < rows * stride; e += kMlpThreads) {
       const int o = e / stride, i = e % stride;
       float w = 0.0f;
@@ -619,7 +835,6 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
         const double u = (2.0 * (double)grid23(wd) + 1.0) * 5.9604644775390625e-8;
         w = (float)((2.0 * u - 1.0) / sqrt((double)fan_in));
       }
-      (void)bound;
       P[off + e] = w;
     }
     if (l <= H)
@@ -652,35 +867,51 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
   }
   __syncthreads();
 
+  const Lanes ln(Smem<U, H>::SW0, Smem<U, H>::SW);
+  const Feeder feed(a, date);
   float best = INFINITY;
   int pos = 0;
-  int t = 0;
   float p1 = 1.0f, p2 = 1.0f;
   for (int epoch = 1; epoch <= a.epochs; ++epoch) {
     for (int64_t b0 = 0; b0 < a.M; b0 += a.batch) {
       const int64_t b1 = min(b0 + (int64_t)a.batch, a.M);
       const float inv_batch = 1.0f / (float)(b1 - b0);
-      f32x4 accW[TT::slots];
+      f32x4 accW[dw_slots(U, H)];
 #pragma unroll
-      for (int s = 0; s < TT::slots; ++s) accW[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      for (int64_t r0 = b0; r0 < b1; r0 += kMlpRows) {
-        const int n = (int)min((int64_t)kMlpRows, b1 - r0);
-        load_chunk<U, H>(S, a, date, r0, n);
+      for (int s = 0; s < dw_slots(U, H); ++s) accW[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      ChunkRegs c = feed.load(b0, (int)min((int64_t)R, b1 - b0));
+      for (int64_t r0 = b0; r0 < b1; r0 += R) {
+        const int n = (int)min((int64_t)R, b1 - r0);
+        const float y = store_chunk<U, H>(S, c, n);
+        if (r0 + R < b1) c = feed.load(r0 + R, (int)min((int64_t)R, b1 - r0 - R));
         __syncthreads();
-        forward<U, H>(S);
-        backward<U, H>(S, n, pos, inv_batch, accW);
+        forward<U, H>(S, ln);
+        if (opaque_tid() < R) {             // wave 0: one row per lane
+          const int r = opaque_tid();
+          const float f = output_of_row<U, H>(S, r);
+          const float pred = (pos ? fmaxf(f, 0.0f) : f) + S.scal()[1];
+          const float dp = r < n ? 2.0f * (pred - y) * inv_batch : 0.0f;
+          const float df = pos ? (f > 0.0f ? dp : 0.0f) : dp;
+          S.dff()[r] = df;
+          const float gm = wave_sum(dp), gb = wave_sum(df);
+          if (r == 0) {
+            S.scal()[3] += gm;
+            S.scal()[2] += gb;
+          }
+        }
+        __syncthreads();
+        backward<U, H>(S, ln, accW);
       }
-      ++t;
       p1 *= a.beta1;
       p2 *= a.beta2;
       const AdamStep st{a.lr, a.beta1, a.beta2, a.eps, 1.0f / (1.0f - p1), 1.0f / (1.0f - p2)};
       adam_update<U, H>(S, L, P, Mm, Vv, st, accW);
     }
     if (epoch == a.epochs / 2) {
-      refit<U, H>(S, a, date, L, P, a.gram + (int64_t)job * (U + 1) * (U + 2));
+      refit<U, H>(S, ln, feed, a, L, P, a.gram + (int64_t)job * (U + 1) * (U + 2));
       pos = 1;
     }
-    const float loss = full_loss<U, H>(S, a, date);
+    const float loss = full_loss<U, H>(S, ln, feed, a);
     if (a.loss_hist && opaque_tid() == 0) a.loss_hist[(int64_t)job * a.epochs + epoch - 1] = loss;
     if (loss < best) {
       best = loss;
@@ -713,17 +944,18 @@ template <int U, int H>
 __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs a, float* out) {
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   Smem<U, H> S{(__bf16*)smem_raw};
+  constexpr int R = kMlpRows;
   const MlpLayout L{U, H};
   const int job = blockIdx.y;
   const int date = a.dates[job];
   const float* rec = a.model + (int64_t)job * L.record();
-  const int64_t rows_per_block = 64 * kMlpRows;
+  const int64_t rows_per_block = 64 * R;
   const int64_t k0 = (int64_t)blockIdx.x * rows_per_block;
   if (k0 >= a.M) return;
+  const int64_t k1 = min(k0 + rows_per_block, a.M);
   const bool trained = rec[L.trained_off()] != 0.0f;
   if (!trained) {
-    for (int64_t k = k0 + opaque_tid(); k < min(k0 + rows_per_block, a.M); k += kMlpThreads)
-      out[(int64_t)job * a.M + k] = 0.0f;
+    for (int64_t k = k0 + opaque_tid(); k < k1; k += kMlpThreads) out[(int64_t)job * a.M + k] = 0.0f;
     return;
   }
   for (int e = opaque_tid(); e < kMlpDin; e += kMlpThreads) {
@@ -734,16 +966,17 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs 
   load_weights<U, H>(S, rec, L);
   __syncthreads();
   const float ysc = rec[L.yscale_off()];
-  for (int64_t r0 = k0; r0 < min(k0 + rows_per_block, a.M); r0 += kMlpRows) {
-    const int n = (int)min((int64_t)kMlpRows, a.M - r0);
-    load_chunk<U, H>(S, a, date, r0, n);
+  const Lanes ln(Smem<U, H>::SW0, Smem<U, H>::SW);
+  const Feeder feed(a, date);
+  ChunkRegs c = feed.load(k0, (int)min((int64_t)R, k1 - k0));
+  for (int64_t r0 = k0; r0 < k1; r0 += R) {
+    const int n = (int)min((int64_t)R, k1 - r0);
+    store_chunk<U, H>(S, c, n);
+    if (r0 + R < k1) c = feed.load(r0 + R, (int)min((int64_t)R, k1 - r0 - R));
     __syncthreads();
-    forward<U, H>(S);
-    if (opaque_tid() < n) {
-      const float f = S.fbuf()[opaque_tid()];
-      out[(int64_t)job * a.M + r0 + opaque_tid()] = ((f > 0.0f ? f : 0.0f) + S.scal()[1]) * ysc;
-    }
-    __syncthreads();
+    forward<U, H>(S, ln);
+    const int t = opaque_tid();
+    if (t < n) out[(int64_t)job * a.M + r0 + t] = (fmaxf(output_of_row<U, H>(S, t), 0.0f) + S.scal()[1]) * ysc;
   }
 }
 
