@@ -228,6 +228,9 @@ typedef struct {
                          in one persistent launch; 1: Backward learning, dates trained one after
                          another in the order given, each started from the previous date's result */
   int32_t init_tag;   /* Philox word selecting the initial draw */
+  int32_t team;       /* workgroups training one date together (0..32); 0: chosen by the library
+                         from the device size, the number of dates and the batch.  Results depend
+                         on it only through the summation order of the batch gradient */
 } cva_mlp_cfg;
 
 /* Floats per date of the model array written by cva_regress_fit (parameters, then scaling). */

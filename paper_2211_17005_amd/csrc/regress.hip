@@ -551,6 +551,48 @@ __device__ void backward(const Smem<U, H>& S, const Lanes& ln, f32x4* accW) {
 }
 
 // ------------------------------------------------------------------------------------------
+// teams: G workgroups training one date together
+// ------------------------------------------------------------------------------------------
+constexpr int kTeamSpinLimit = 1 << 22;   // polls before a team barrier gives up (several seconds)
+
+// Barrier of the G workgroups of a team: a monotonic arrival counter in global memory.  Every
+// thread publishes its global writes at device scope before its workgroup arrives; after the
+// wait every wave invalidates its stale cached lines.  All workgroups of a launch are resident
+// (cooperative launch), so the wait ends; should it not within the poll limit, the workgroup
+// marks itself failed, stops waiting at later barriers (it still arrives) and leaves the fit at
+// the end of the epoch with a NaN loss, so a launch always terminates.
+struct Team {
+  int32_t* ctr;
+  int G, member, arrivals;
+  bool failed;
+  __device__ void sync() {
+    if (G == 1) {
+      __syncthreads();
+      return;
+    }
+    __threadfence();
+    __syncthreads();
+    ++arrivals;
+    __shared__ int s_failed;
+    if (threadIdx.x == 0) {
+      __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      const int target = arrivals * G;
+      int polls = failed ? kTeamSpinLimit : 0;
+      while (polls < kTeamSpinLimit &&
+             __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        ++polls;
+      }
+      s_failed = polls == kTeamSpinLimit &&
+                 __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target;
+    }
+    __syncthreads();
+    failed = failed || s_failed;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+};
+
+// ------------------------------------------------------------------------------------------
 // Adam
 // ------------------------------------------------------------------------------------------
 struct AdamStep {
@@ -630,19 +672,81 @@ __device__ void adam_update(const Smem<U, H>& S, const MlpLayout& L, float* P, f
   __syncthreads();
 }
 
+// One Adam step of a team: every workgroup publishes its batch gradient in parameter order,
+// each member sums the G gradients of its slice of the parameters (fixed order) and updates that
+// slice, and every workgroup reloads the new parameters.
+template <int U, int H, int L>
+__device__ void publish_dw(const MlpLayout& Lay, float* part, f32x4* accW) {
+  using M = DwMap<U, L>;
+  constexpr int K = L == 1 ? kMlpDin : U;
+  const int wave = wave_id(), lane = lane_id();
+  const int ib = wave % M::NIB, ob = wave / M::NIB;
+  if (ob >= M::NOB) return;
+  f32x4* acc = accW + dw_base(U, L);
+#pragma unroll
+  for (int x = 0; x < M::BO; ++x)
+#pragma unroll
+    for (int y = 0; y < M::BI; ++y) {
+      const int s = x * M::BI + y, ot = ob * M::BO + x, it = ib * M::BI + y;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        part[Lay.w_off(L) + (16 * ot + 4 * (lane / 16) + v) * K + 16 * it + lane % 16] = acc[s][v];
+      acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+}
+
+template <int U, int H>
+__device__ void team_step(const Smem<U, H>& S, const MlpArgs& a, Team& tm, int team, const MlpLayout& L,
+                          float* P, float* Mm, float* Vv, const AdamStep& st, f32x4* accW) {
+  const int NP = L.n_params();
+  float* part = a.partial + ((int64_t)team * tm.G + tm.member) * NP;
+  publish_dw<U, H, 1>(L, part, accW);
+  if constexpr (H >= 2) publish_dw<U, H, 2>(L, part, accW);
+  if constexpr (H >= 3) publish_dw<U, H, 3>(L, part, accW);
+  for (int l = 1; l <= H; ++l)
+    for (int u = opaque_tid(); u < U; u += kMlpThreads) {
+      part[L.b_off(l) + u] = S.gbias(l)[u];
+      S.gbias(l)[u] = 0.0f;
+    }
+  for (int u = opaque_tid(); u < U; u += kMlpThreads) {
+    part[L.wout_off() + u] = S.gwout()[u];
+    S.gwout()[u] = 0.0f;
+  }
+  if (opaque_tid() == 0) {
+    part[L.bout_off()] = S.scal()[2];
+    part[L.mu_off()] = S.scal()[3];
+    S.scal()[2] = 0.0f;
+    S.scal()[3] = 0.0f;
+  }
+  tm.sync();
+  const float* part0 = a.partial + (int64_t)team * tm.G * NP;
+  const int lo = (int)((int64_t)NP * tm.member / tm.G), hi = (int)((int64_t)NP * (tm.member + 1) / tm.G);
+  for (int p = lo + opaque_tid(); p < hi; p += kMlpThreads) {
+    float g = 0.0f;
+    for (int j = 0; j < tm.G; ++j) g += part0[(int64_t)j * NP + p];
+    P[p] = st(P[p], g, &Mm[p], &Vv[p]);
+  }
+  tm.sync();
+  load_weights<U, H>(S, P, L);
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------------------------------
 // full-sample passes: loss and refit
 // ------------------------------------------------------------------------------------------
 // Full-sample loss with the output ReLU (pos = 1).
 template <int U, int H>
-__device__ float full_loss(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, const MlpArgs& a) {
+__device__ float full_loss(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, const MlpArgs& a, Team& tm,
+                           int team) {
   constexpr int R = kMlpRows;
+  const int64_t stride = (int64_t)R * tm.G;
   double e = 0.0;
-  ChunkRegs c = feed.load(0, (int)min((int64_t)R, a.M));
-  for (int64_t r0 = 0; r0 < a.M; r0 += R) {
+  const int64_t first = (int64_t)R * tm.member;
+  ChunkRegs c = feed.load(first, (int)max((int64_t)0, min((int64_t)R, a.M - first)));
+  for (int64_t r0 = first; r0 < a.M; r0 += stride) {
     const int n = (int)min((int64_t)R, a.M - r0);
     const float y = store_chunk<U, H>(S, c, n);
-    if (r0 + R < a.M) c = feed.load(r0 + R, (int)min((int64_t)R, a.M - r0 - R));
+    if (r0 + stride < a.M) c = feed.load(r0 + stride, (int)min((int64_t)R, a.M - r0 - stride));
     __syncthreads();
     forward<U, H>(S, ln);
     const int t = opaque_tid();
@@ -659,15 +763,23 @@ __device__ float full_loss(const Smem<U, H>& S, const Lanes& ln, const Feeder& f
     if (opaque_tid() < w) red[opaque_tid()] += red[opaque_tid() + w];
     __syncthreads();
   }
-  const float L = (float)(red[0] / (double)a.M);
+  double sum = red[0];
   __syncthreads();
-  return L;
+  if (tm.G > 1) {
+    double* lp = a.loss_part + (int64_t)team * tm.G;
+    if (opaque_tid() == 0) lp[tm.member] = sum;
+    tm.sync();
+    sum = 0.0;
+    for (int j = 0; j < tm.G; ++j) sum += lp[j];
+  }
+  return (float)(sum / (double)a.M);
 }
 
 // Least-squares refit of (w_out, b_out) on the frozen hidden features, mu fixed.
 template <int U, int H>
 __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, const MlpArgs& a,
-                      const MlpLayout& L, float* P, double* G) {
+                      const MlpLayout& L, float* P, Team& tm, int team) {
+  double* G = a.gram + ((int64_t)team * tm.G + tm.member) * (U + 1) * (U + 2);
   constexpr int NT = U / 16, NG = NT * NT, GS = (NG + kMlpWaves - 1) / kMlpWaves, N = U + 1;
   constexpr int R = kMlpRows;
   const int tid = opaque_tid(), wave = wave_id(), lane = lane_id();
@@ -680,11 +792,12 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
     for (int v = 0; v < 4; ++v) accG[s][v] = 0.0;
   double hs = 0.0, hy = 0.0, ys = 0.0;        // thread u: sum h_u, sum h_u (y - mu); thread U: sum (y - mu)
   const float mu = S.scal()[1];
-  ChunkRegs c = feed.load(0, (int)min((int64_t)R, a.M));
-  for (int64_t r0 = 0; r0 < a.M; r0 += R) {
+  const int64_t stride = (int64_t)R * tm.G, first = (int64_t)R * tm.member;
+  ChunkRegs c = feed.load(first, (int)max((int64_t)0, min((int64_t)R, a.M - first)));
+  for (int64_t r0 = first; r0 < a.M; r0 += stride) {
     const int n = (int)min((int64_t)R, a.M - r0);
     store_chunk<U, H>(S, c, n);
-    if (r0 + R < a.M) c = feed.load(r0 + R, (int)min((int64_t)R, a.M - r0 - R));
+    if (r0 + stride < a.M) c = feed.load(r0 + stride, (int)min((int64_t)R, a.M - r0 - stride));
     __syncthreads();
     forward<U, H>(S, ln);
     __bf16* Hh = S.A(H);
@@ -732,8 +845,20 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
     G[U * N + tid] = hs;
     rhs[tid] = hy;
   } else if (tid == U) {
-    G[U * N + U] = (double)a.M;
+    G[U * N + U] = (double)(tm.member == 0 ? a.M : 0);
     rhs[U] = ys;
+  }
+  tm.sync();
+  if (tm.member != 0) {                 // the first workgroup solves; the others wait for w_out
+    tm.sync();
+    for (int u = opaque_tid(); u < U; u += kMlpThreads) S.wout()[u] = P[L.wout_off() + u];
+    if (opaque_tid() == 0) S.scal()[0] = P[L.bout_off()];
+    __syncthreads();
+    return;
+  }
+  for (int j = 1; j < tm.G; ++j) {      // sum of the partial normal equations, fixed order
+    const double* Gj = G + (int64_t)j * (U + 1) * (U + 2);
+    for (int e = opaque_tid(); e < N * N + N; e += kMlpThreads) G[e] += Gj[e];
   }
   __threadfence_block();
   __syncthreads();
@@ -796,13 +921,14 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
   }
   __threadfence_block();
   __syncthreads();
+  if (tm.G > 1) tm.sync();
 }
 
 // ------------------------------------------------------------------------------------------
 // BaseAlg for one date
 // ------------------------------------------------------------------------------------------
 template <int U, int H>
-__device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
+__device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& tm, int team) {
   constexpr int R = kMlpRows;
   const MlpLayout L{U, H};
   const int date = a.dates[job];
@@ -817,8 +943,8 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
   }
   if (opaque_tid() == 0) S.scal()[4] = rec[L.yscale_off()];
   const bool trained = rec[L.trained_off()] != 0.0f;
-  // initial parameters
-  for (int l = 1; l <= H + 1; ++l) {
+  // initial parameters (written by the first workgroup of the team)
+  for (int l = 1; l <= H + 1 && tm.member == 0; ++l) {
     const int fan_in = l == 1 ? a.d_in : U;
     const int rows = l <= H ? U : 1;
     const int stride = l == 1 ? kMlpDin : U;
@@ -840,21 +966,25 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
     if (l <= H)
       for (int e = opaque_tid(); e < U; e += kMlpThreads) P[L.b_off(l) + e] = a.use_init ? rec[L.b_off(l) + e] : 0.0f;
   }
-  if (opaque_tid() == 0) {
-    P[L.bout_off()] = a.use_init ? rec[L.bout_off()] : 0.0f;
-    P[L.mu_off()] = a.use_init ? rec[L.mu_off()] : 0.0f;
-  }
-  for (int e = opaque_tid(); e < NP; e += kMlpThreads) {
-    Mm[e] = 0.0f;
-    Vv[e] = 0.0f;
+  if (tm.member == 0) {
+    if (opaque_tid() == 0) {
+      P[L.bout_off()] = a.use_init ? rec[L.bout_off()] : 0.0f;
+      P[L.mu_off()] = a.use_init ? rec[L.mu_off()] : 0.0f;
+    }
+    for (int e = opaque_tid(); e < NP; e += kMlpThreads) {
+      Mm[e] = 0.0f;
+      Vv[e] = 0.0f;
+    }
   }
   __threadfence_block();
-  __syncthreads();
+  tm.sync();
   if (!trained) {
-    for (int e = opaque_tid(); e < NP; e += kMlpThreads) rec[e] = P[e];
-    if (a.loss_hist)
-      for (int e = opaque_tid(); e < a.epochs; e += kMlpThreads) a.loss_hist[(int64_t)job * a.epochs + e] = 0.0f;
-    __syncthreads();
+    if (tm.member == 0) {
+      for (int e = opaque_tid(); e < NP; e += kMlpThreads) rec[e] = P[e];
+      if (a.loss_hist)
+        for (int e = opaque_tid(); e < a.epochs; e += kMlpThreads) a.loss_hist[(int64_t)job * a.epochs + e] = 0.0f;
+    }
+    tm.sync();
     return;
   }
   load_weights<U, H>(S, P, L);
@@ -872,6 +1002,7 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
   float best = INFINITY;
   int pos = 0;
   float p1 = 1.0f, p2 = 1.0f;
+  const int64_t cstride = (int64_t)R * tm.G;   // this workgroup's chunks of a batch
   for (int epoch = 1; epoch <= a.epochs; ++epoch) {
     for (int64_t b0 = 0; b0 < a.M; b0 += a.batch) {
       const int64_t b1 = min(b0 + (int64_t)a.batch, a.M);
@@ -879,11 +1010,12 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
       f32x4 accW[dw_slots(U, H)];
 #pragma unroll
       for (int s = 0; s < dw_slots(U, H); ++s) accW[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      ChunkRegs c = feed.load(b0, (int)min((int64_t)R, b1 - b0));
-      for (int64_t r0 = b0; r0 < b1; r0 += R) {
+      const int64_t first = b0 + (int64_t)R * tm.member;
+      ChunkRegs c = feed.load(first, (int)max((int64_t)0, min((int64_t)R, b1 - first)));
+      for (int64_t r0 = first; r0 < b1; r0 += cstride) {
         const int n = (int)min((int64_t)R, b1 - r0);
         const float y = store_chunk<U, H>(S, c, n);
-        if (r0 + R < b1) c = feed.load(r0 + R, (int)min((int64_t)R, b1 - r0 - R));
+        if (r0 + cstride < b1) c = feed.load(r0 + cstride, (int)min((int64_t)R, b1 - r0 - cstride));
         __syncthreads();
         forward<U, H>(S, ln);
         if (opaque_tid() < R) {             // wave 0: one row per lane
@@ -905,38 +1037,43 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job) {
       p1 *= a.beta1;
       p2 *= a.beta2;
       const AdamStep st{a.lr, a.beta1, a.beta2, a.eps, 1.0f / (1.0f - p1), 1.0f / (1.0f - p2)};
-      adam_update<U, H>(S, L, P, Mm, Vv, st, accW);
+      if (tm.G == 1)
+        adam_update<U, H>(S, L, P, Mm, Vv, st, accW);
+      else
+        team_step<U, H>(S, a, tm, team, L, P, Mm, Vv, st, accW);
     }
     if (epoch == a.epochs / 2) {
-      refit<U, H>(S, ln, feed, a, L, P, a.gram + (int64_t)job * (U + 1) * (U + 2));
+      refit<U, H>(S, ln, feed, a, L, P, tm, team);
       pos = 1;
     }
-    const float loss = full_loss<U, H>(S, ln, feed, a);
-    if (a.loss_hist && opaque_tid() == 0) a.loss_hist[(int64_t)job * a.epochs + epoch - 1] = loss;
+    float loss = full_loss<U, H>(S, ln, feed, a, tm, team);
+    if (tm.failed) loss = NAN;
+    if (a.loss_hist && (tm.member == 0 || tm.failed) && opaque_tid() == 0)
+      a.loss_hist[(int64_t)job * a.epochs + epoch - 1] = loss;
+    if (tm.failed) return;
     if (loss < best) {
       best = loss;
       __threadfence_block();
       __syncthreads();
-      for (int e = opaque_tid(); e < NP; e += kMlpThreads) rec[e] = P[e];
+      if (tm.member == 0)
+        for (int e = opaque_tid(); e < NP; e += kMlpThreads) rec[e] = P[e];
     }
     __syncthreads();
   }
 }
 
+// Workgroup b belongs to team (b % 8) + 8 ((b / 8) / G) as member (b / 8) % G: consecutive
+// workgroups go to different XCDs, so the members of a team share one XCD (and its L2).  Teams
+// take the dates team, team + n_teams, ...
 template <int U, int H>
 __global__ __launch_bounds__(kMlpThreads) void mlp_train_kernel(const MlpArgs a) {
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   Smem<U, H> S{(__bf16*)smem_raw};
-  __shared__ int s_job;
-  for (;;) {
-    if (opaque_tid() == 0) s_job = atomicAdd(a.queue, 1);
-    __syncthreads();
-    const int job = s_job;
-    __syncthreads();
-    if (job >= a.n_reg) break;
-    train_one<U, H>(S, a, job);
-    __syncthreads();
-  }
+  const int b = blockIdx.x;
+  const int team = b % 8 + 8 * ((b / 8) / a.G), member = (b / 8) % a.G;
+  if (team >= a.n_teams) return;
+  Team tm{a.team_ctr + team, a.G, member, 0, false};
+  for (int job = team; job < a.n_reg && !tm.failed; job += a.n_teams) train_one<U, H>(S, a, job, tm, team);
 }
 
 // Prediction with the best parameters: out[job][k] = ((f)^+ + mu) * y_scale (0 if untrained).
@@ -980,8 +1117,6 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs 
   }
 }
 
-__global__ void fill_i32(int32_t* p, int32_t v) { p[opaque_tid()] = v; }
-
 #define HSIM_MLP_SHAPES(X) X(32, 1) X(32, 2) X(64, 2) X(128, 2) X(128, 3)
 
 bool mlp_supported(int U, int H) {
@@ -996,15 +1131,41 @@ hipError_t launch_mlp_stats(const MlpArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_train(const MlpArgs& a, int n_workgroups, hipStream_t s) {
-  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(1), 0, s, a.queue, 0);
+__global__ void zero_i32(int32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+int mlp_max_teams(int U, int H, int G) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+#define X(u, h)                                                                                  \
+  if (U == u && H == h) {                                                                        \
+    hipFuncSetAttribute((const void*)mlp_train_kernel<u, h>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                        Smem<u, h>::bytes);                                                      \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mlp_train_kernel<u, h>, kMlpThreads, \
+                                                     Smem<u, h>::bytes) != hipSuccess)           \
+      return 0;                                                                                  \
+  }
+  HSIM_MLP_SHAPES(X)
+#undef X
+  if (G < 1) return 0;
+  return 8 * ((ncu * per_cu) / (8 * G));   // whole groups of 8 teams (one per XCD)
+}
+
+hipError_t launch_mlp_train(const MlpArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, a.team_ctr, a.n_teams);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned grid = 8u * (unsigned)a.G * (unsigned)((a.n_teams + 7) / 8);
+  void* args[] = {(void*)&a};
 #define X(u, h)                                                                                  \
   if (a.U == u && a.H == h) {                                                                    \
     const int bytes = Smem<u, h>::bytes;                                                         \
     hipFuncSetAttribute((const void*)mlp_train_kernel<u, h>,                                     \
                         hipFuncAttributeMaxDynamicSharedMemorySize, bytes);                      \
-    hipLaunchKernelGGL((mlp_train_kernel<u, h>), dim3(n_workgroups), dim3(kMlpThreads), bytes, s, a); \
-    return hipGetLastError();                                                                    \
+    return hipLaunchCooperativeKernel((const void*)mlp_train_kernel<u, h>, dim3(grid), dim3(kMlpThreads), \
+                                      args, bytes, s);                                           \
   }
   HSIM_MLP_SHAPES(X)
 #undef X

@@ -6,7 +6,7 @@
 
 namespace hsim {
 
-constexpr int kMlpThreads = 512;     // 8 waves per workgroup, one workgroup per date
+constexpr int kMlpThreads = 512;     // 8 waves per workgroup; a team of workgroups per date
 constexpr int kMlpWaves = kMlpThreads / 64;
 constexpr int kMlpRows = 64;         // rows of a chunk staged in LDS
 constexpr int kMlpDin = 32;          // input width, padded to one MFMA K step
@@ -46,18 +46,25 @@ struct MlpArgs {
   const float* X;                 // [n+1][n_feat][M]
   const float* Y;                 // [n+1][M]
   float* model;                   // [n_reg][record]   (best parameters + scaling)
-  float* cur;                     // [n_reg][n_params] current parameters
+  float* cur;                     // [n_reg][n_params] current parameters (one copy per team)
   float* adam_m;                  // [n_reg][n_params]
   float* adam_v;                  // [n_reg][n_params]
-  double* gram;                   // [n_reg][(U+1)*(U+2)]  refit normal equations
+  float* partial;                 // [n_teams][G][n_params] per-workgroup gradients (G > 1)
+  double* gram;                   // [n_teams][G][(U+1)*(U+2)] refit normal equations
+  double* loss_part;              // [n_teams][G] per-workgroup loss sums
+  int32_t* team_ctr;              // [n_teams] barrier arrivals (zeroed before the launch)
   float* loss_hist;               // [n_reg][epochs] or null
-  int32_t* queue;                 // work counter (zeroed before the launch)
+  int32_t G;                      // workgroups per team (one team trains one date at a time)
+  int32_t n_teams;
   int32_t use_init;               // 1: start from `model` (warm start), 0: from the Philox draw
   int32_t dates[kMaxRegDates];
 };
 
 hipError_t launch_mlp_stats(const MlpArgs& a, hipStream_t s);
-hipError_t launch_mlp_train(const MlpArgs& a, int n_workgroups, hipStream_t s);
+// Teams that fit on the device at once for team size G (all workgroups of a launch are resident).
+int mlp_max_teams(int U, int H, int G);
+// Launch with a.G, a.n_teams set (a.n_teams <= mlp_max_teams); zeroes the team counters first.
+hipError_t launch_mlp_train(const MlpArgs& a, hipStream_t s);
 hipError_t launch_mlp_predict(const MlpArgs& a, float* out, hipStream_t s);
 bool mlp_supported(int U, int H);
 

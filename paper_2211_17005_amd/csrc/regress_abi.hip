@@ -17,6 +17,7 @@ int check_cfg(const cva_mlp_cfg* c) {
     return fail(HSIM_EUNSUPPORTED, "no kernel built for width=%d hidden=%d", c->width, c->hidden);
   if (c->d_in < 1 || c->d_in > kMlpDin) return fail(HSIM_ERANGE, "d_in=%d out of [1,%d]", c->d_in, kMlpDin);
   if (c->epochs < 1 || c->batch < 1) return fail(HSIM_EINVAL, "epochs and batch must be >= 1");
+  if (c->team < 0 || c->team > 32) return fail(HSIM_ERANGE, "team=%d out of [0,32]", c->team);
   if (!(c->lr > 0.0f) || !(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f) ||
       !(c->eps > 0.0f))
     return fail(HSIM_EINVAL, "bad Adam hyper-parameters");
@@ -51,11 +52,42 @@ int fill_args(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int32_t
   return HSIM_OK;
 }
 
-int n_cus() {
-  int dev = 0, n = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  return n;
+// Team size (workgroups per date) and number of teams of one training launch over n_dates dates:
+// the configured size, else as many workgroups per date as the device holds for all dates at
+// once, at most one per four chunks of a batch and at most 32 (one XCD).
+bool choose_team(const cva_mlp_cfg* c, int n_dates, int& G, int& n_teams) {
+  const int chunks = (c->batch + kMlpRows - 1) / kMlpRows;
+  const int resident = mlp_max_teams(c->width, c->hidden, 1);
+  if (resident <= 0) return false;
+  if (c->team > 0) {
+    G = c->team;
+  } else {
+    G = resident / n_dates;
+    G = G < chunks / 4 ? G : chunks / 4;
+    G = G < 32 ? G : 32;
+    G = G > 1 ? G : 1;
+  }
+  const int max_teams = mlp_max_teams(c->width, c->hidden, G);
+  if (max_teams <= 0) return false;
+  n_teams = n_dates < max_teams ? n_dates : max_teams;
+  return true;
+}
+
+struct RegWs {
+  size_t params, partial, gram, loss, ctr, total;
+};
+
+RegWs reg_ws(const cva_mlp_cfg* c, int n_reg, int G, int n_teams) {
+  const MlpLayout L{c->width, c->hidden};
+  const size_t np = (size_t)L.n_params();
+  RegWs w;
+  w.params = align256(3 * np * n_reg * sizeof(float));
+  w.partial = align256(G > 1 ? np * G * n_teams * sizeof(float) : 0);
+  w.gram = align256((size_t)(c->width + 1) * (c->width + 2) * G * n_teams * sizeof(double));
+  w.loss = align256((size_t)G * n_teams * sizeof(double));
+  w.ctr = align256((size_t)n_teams * sizeof(int32_t));
+  w.total = w.params + w.partial + w.gram + w.loss + w.ctr;
+  return w;
 }
 
 __global__ void copy_params(const float* src, float* dst, int n) {
@@ -74,11 +106,10 @@ int cva_regress_record_floats(const cva_mlp_cfg* c) {
 
 size_t cva_regress_workspace_bytes(const cva_mlp_cfg* c, int32_t n_reg, int64_t M) {
   (void)M;
-  if (!c || n_reg < 1) return 0;
-  const MlpLayout L{c->width, c->hidden};
-  const size_t np = (size_t)L.n_params();
-  return align256(3 * np * n_reg * sizeof(float)) +
-         align256((size_t)(c->width + 1) * (c->width + 2) * n_reg * sizeof(double)) + 256;
+  if (!c || n_reg < 1 || check_cfg(c) != HSIM_OK) return 0;
+  int G = 0, n_teams = 0;
+  if (!choose_team(c, c->warm_start ? 1 : n_reg, G, n_teams)) return 0;
+  return reg_ws(c, n_reg, G, n_teams).total;
 }
 
 int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int32_t n_dates_total, int64_t M,
@@ -88,18 +119,27 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
   int rc = fill_args(c, n_reg, dates, n_dates_total, M, n_feat, a);
   if (rc) return rc;
   if (!X_dev || !Y_dev || !model_dev) return fail(HSIM_EINVAL, "X, Y and model must not be NULL");
-  const size_t need = cva_regress_workspace_bytes(c, n_reg, M);
-  if (!workspace_dev || ws_bytes < need) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, need);
+  int G = 0, n_teams = 0;
+  if (!choose_team(c, c->warm_start ? 1 : n_reg, G, n_teams))
+    return fail(HSIM_EDEVICE, "no team of %d workgroups fits on the device", c->team);
+  const RegWs ws = reg_ws(c, n_reg, G, n_teams);
+  if (!workspace_dev || ws_bytes < ws.total) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, ws.total);
   const MlpLayout L{c->width, c->hidden};
   const size_t np = (size_t)L.n_params();
   char* w = (char*)workspace_dev;
   a.cur = (float*)w;
   a.adam_m = a.cur + np * n_reg;
   a.adam_v = a.adam_m + np * n_reg;
-  w += align256(3 * np * n_reg * sizeof(float));
+  w += ws.params;
+  a.partial = (float*)w;
+  w += ws.partial;
   a.gram = (double*)w;
-  w += align256((size_t)(c->width + 1) * (c->width + 2) * n_reg * sizeof(double));
-  a.queue = (int32_t*)w;
+  w += ws.gram;
+  a.loss_part = (double*)w;
+  w += ws.loss;
+  a.team_ctr = (int32_t*)w;
+  a.G = G;
+  a.n_teams = n_teams;
   a.X = X_dev;
   a.Y = Y_dev;
   a.model = model_dev;
@@ -111,9 +151,7 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
   if (e != hipSuccess) return device_error(e, "regression statistics launch");
   if (!c->warm_start) {
     a.use_init = 0;
-    int ncu = n_cus();
-    if (ncu <= 0) return fail(HSIM_EDEVICE, "cannot query the number of compute units");
-    e = launch_mlp_train(a, n_reg < ncu ? n_reg : ncu, s);
+    e = launch_mlp_train(a, s);
     if (e != hipSuccess) return device_error(e, "regression training launch");
     return HSIM_OK;
   }
@@ -126,7 +164,6 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
     b.cur = a.cur + np * j;
     b.adam_m = a.adam_m + np * j;
     b.adam_v = a.adam_v + np * j;
-    b.gram = a.gram + (size_t)(c->width + 1) * (c->width + 2) * j;
     b.loss_hist = a.loss_hist ? a.loss_hist + (size_t)c->epochs * j : nullptr;
     b.use_init = j > 0;
     if (j > 0) {
@@ -134,7 +171,7 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
                          b.model, (int)np);
       if ((e = hipGetLastError()) != hipSuccess) return device_error(e, "warm-start copy");
     }
-    e = launch_mlp_train(b, 1, s);
+    e = launch_mlp_train(b, s);
     if (e != hipSuccess) return device_error(e, "regression training launch");
   }
   return HSIM_OK;

@@ -49,7 +49,8 @@ class MlpCfg(ctypes.Structure):
     _fields_ = [("hidden", ctypes.c_int32), ("width", ctypes.c_int32), ("d_in", ctypes.c_int32),
                 ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("warm_start", ctypes.c_int32), ("init_tag", ctypes.c_int32)]
+                ("warm_start", ctypes.c_int32), ("init_tag", ctypes.c_int32),
+                ("team", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -352,12 +353,14 @@ def inner_defaults_cva(w, precision: int = HSIM_FP32, path_begin: int = 0, M=Non
 
 
 # ------------------------------------------------------------------------------- regression
-def mlp_cfg(mlp, d_in: int, M: int, warm_start: bool = False, init_tag: int = 0) -> MlpCfg:
-    """C config from a workload's MLP settings (batch = M / n_batches when no batch is given)."""
+def mlp_cfg(mlp, d_in: int, M: int, warm_start: bool = False, init_tag: int = 0,
+            team: int = 0) -> MlpCfg:
+    """C config from a workload's MLP settings (batch = M / n_batches when no batch is given);
+    team = workgroups per date (0: the library's choice)."""
     batch = int(mlp.batch) if getattr(mlp, "batch", None) else max(1, M // int(mlp.n_batches))
     return MlpCfg(int(mlp.hidden), int(mlp.width), int(d_in), int(mlp.epochs), batch,
                   float(mlp.lr), float(mlp.beta1), float(mlp.beta2), float(mlp.eps),
-                  1 if warm_start else 0, int(init_tag))
+                  1 if warm_start else 0, int(init_tag), int(team))
 
 
 def record_floats(cfg: MlpCfg) -> int:

@@ -49,12 +49,12 @@ def data_big():
     return w, r
 
 
-def fit_both(lib, w, r, mlp, dates, warm):
+def fit_both(lib, w, r, mlp, dates, warm, team=0):
     import torch
     X = torch.as_tensor(r["features"].astype(np.float32), device="cuda")
     Y = torch.as_tensor(r["T"].astype(np.float32), device="cuda")
     d_in = r["features"].shape[1]
-    cfg = lib.mlp_cfg(mlp, d_in, w.M, warm_start=warm)
+    cfg = lib.mlp_cfg(mlp, d_in, w.M, warm_start=warm, team=team)
     model, loss, _ = lib.regress_fit(cfg, dates, X, Y, seed=w.seed)
     pred = npy(lib.regress_predict(cfg, dates, X, model)).astype(np.float64)
     if warm:
@@ -81,9 +81,42 @@ def test_independent_fits_match_oracle(lib, data, data_big, width, hidden, big):
         assert abs(loss[j][-1] - loss_ref[j][-1]) <= 1e-2 * loss_ref[j][-1]
 
 
-def test_backward_learning_matches_oracle(lib, data):
-    w, r = data
-    mlp = wl.MLPConfig(hidden=2, width=32, epochs=4, batch=256)
+@pytest.mark.parametrize("team", [1, 2, 3, 8])
+def test_team_sizes_match_oracle(lib, data_big, team):
+    """A date trained by a team of workgroups (batch gradient summed across them) matches the
+    FP64 fit like a single workgroup does; 16 chunks per batch, so team 3 leaves members with
+    unequal shares and team 8 two chunks each."""
+    w, r = data_big
+    mlp = wl.MLPConfig(hidden=2, width=32, epochs=4, batch=1024)
+    dates = [3, 10, 15]
+    pred, ref, loss, loss_ref = fit_both(lib, w, r, mlp, dates, warm=False, team=team)
+    for j, i in enumerate(dates):
+        l2, mx = rel_errs(pred[j], ref[j])
+        print(f"  team {team} date {i}: l2 {l2:.3e} max {mx:.3e}; loss gpu {loss[j][-1]:.5f} "
+              f"fp64 {loss_ref[j][-1]:.5f}", flush=True)
+        assert np.all(np.isfinite(loss[j]))
+        assert l2 <= TOL
+        assert abs(loss[j][-1] - loss_ref[j][-1]) <= 1e-2 * loss_ref[j][-1]
+
+
+def test_team_fit_is_deterministic(lib, data_big):
+    import torch
+    w, r = data_big
+    X = torch.as_tensor(r["features"].astype(np.float32), device="cuda")
+    Y = torch.as_tensor(r["T"].astype(np.float32), device="cuda")
+    mlp = wl.MLPConfig(hidden=2, width=32, epochs=2, batch=1024)
+    cfg = lib.mlp_cfg(mlp, X.shape[1], w.M, team=3)
+    m1, l1, _ = lib.regress_fit(cfg, [5, 6, 7], X, Y)
+    m2, l2, _ = lib.regress_fit(cfg, [5, 6, 7], X, Y)
+    assert torch.equal(m1, m2) and torch.equal(l1, l2)
+
+
+@pytest.mark.parametrize("big", [False, True])
+def test_backward_learning_matches_oracle(lib, data, data_big, big):
+    """Algorithm 2 (one date after another, warm-started); on the larger sample every date is
+    trained by a team of four workgroups (16 chunks per batch)."""
+    w, r = data_big if big else data
+    mlp = wl.MLPConfig(hidden=2, width=32, epochs=4, batch=1024 if big else 256)
     dates = [12, 11, 10]
     pred, ref, _, _ = fit_both(lib, w, r, mlp, dates, warm=True)
     for j, i in enumerate(dates):
