@@ -78,31 +78,88 @@ def mlp_flops_per_date(d_in: int, width: int, hidden: int, M: int, epochs: int) 
     return epochs * M * (train + fwd) + M * (fwd + 2.0 * (U + 1) ** 2)
 
 
+def profiled_traffic(key: str, source: str):
+    """HBM bytes per launch of a kernel from the committed counter summaries (profiles/*.md),
+    or None when no summary covers it or its source file has changed since the counters were
+    taken (the summary records the sha256 of that file)."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2211_17005_amd", "csrc", source)
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        value, sha = None, None
+        for line in open(f):
+            parts = line.split()
+            if len(parts) == 3 and parts[0] == "traffic_bytes_per_launch" and parts[1] == key:
+                value = float(parts[2])
+            if len(parts) == 2 and parts[0] == "source_sha256":
+                sha = parts[1]
+        if value is not None and sha == digest:
+            return value
+    return None
+
+
 # ------------------------------------------------------------------------------- CPU baseline
-def _oracle_chunk(args):
-    name, kw, begin, count = args
-    from oracle import pipeline
+def _oracle_sample(args):
+    """One worker's share of the bounded oracle sample: simulation of `n_sim` paths, one
+    BaseAlg epoch pair on `n_rows` rows of one date, CVA_0 of `n_sens` paths (the unit of the
+    oracle's central-difference gradient).  Returns the three times."""
+    name, kw, k, n_sim, n_rows, n_sens = args
+    from threadpoolctl import threadpool_limits
+    from oracle import pipeline, regression, sensitivities
     w = wl.get(name, **kw)
-    t = time.perf_counter()
-    pipeline.simulate(w, path_begin=begin, count=count, chunk=count)
-    return time.perf_counter() - t
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        r = pipeline.simulate(w, path_begin=k * n_sim, count=n_sim, chunk=min(n_sim, 320))
+        t_sim = time.perf_counter() - t
+        # regression sample: the simulated features of this worker's date, tiled to n_rows
+        wr = wl.precision_form(M=n_rows)
+        i = 1 + k % w.grid.n_dates
+        reps = -(-n_rows // r["T"].shape[1])
+        X = np.tile(r["features"][i].T, (reps, 1))[:n_rows]
+        y = np.tile(r["T"][i], reps)[:n_rows] + 1.0
+        cfg = wr.mlp
+        t = time.perf_counter()
+        net = regression.init_net(X.shape[1], cfg.hidden, cfg.width, 0)
+        regression.fit_date(X, y, type(cfg)(**{**cfg.__dict__, "epochs": 1}), net, cfg.batch)
+        t_reg = time.perf_counter() - t
+        ws = wl.differentiation_form()
+        t = time.perf_counter()
+        sensitivities.cva0_smoothed(ws, np.arange(k * n_sens, (k + 1) * n_sens))
+        t_sens = time.perf_counter() - t
+    return t_sim, t_reg, t_sens
 
 
-def cpu_baseline(w, name, kw, paths_per_worker: int, workers: int):
-    """The FP64 oracle on `workers * paths_per_worker` paths, one chunk per process."""
+def cpu_baseline(w, name, kw, workers: int, n_sim: int, n_rows: int, n_sens: int):
+    """The FP64 oracle on a bounded sample of the solve, one share per process (all in
+    parallel), each stage scaled to the full step: simulation of M paths, 50 epochs of BaseAlg
+    on M rows at every trained date, and the 2 x 90 CVA_0 evaluations of the oracle's central
+    differences on the 2^16 sensitivity paths."""
     import multiprocessing as mp
     ctx = mp.get_context("fork")          # runs before the GPU is initialised
-    jobs = [(name, kw, i * paths_per_worker, paths_per_worker) for i in range(workers)]
+    jobs = [(name, kw, k, n_sim, n_rows, n_sens) for k in range(workers)]
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
-        pool.map(_oracle_chunk, jobs)
+        times = np.array(pool.map(_oracle_sample, jobs))
     wall = time.perf_counter() - t0
-    n_paths = workers * paths_per_worker
-    rate = n_paths * w.n_b * w.grid.n_dates / wall
+    t_sim, t_reg, t_sens = times.mean(axis=0)      # per worker, all workers in parallel
+    wr = wl.precision_form(M=w.M)
+    ws = wl.differentiation_form()
+    from oracle import sensitivities
+    n_par = sensitivities.pack(ws.market).size
+    dates = w.grid.n_dates - 1
+    est = (t_sim * w.M / (workers * n_sim)
+           + t_reg * (dates * w.M * wr.mlp.epochs) / (workers * n_rows * 1)
+           + t_sens * (2 * n_par * ws.M) / (workers * n_sens))
+    rate = w.M * w.n_b * w.grid.n_dates / est
     return {"value": rate, "unit": "path-steps/s", "cores": workers, "kind": "oracle",
-            "sample": f"{n_paths} outer paths x n_b={w.n_b} of the same workload (simulation, "
-                      f"pricing, inner draws, targets; the regression and sensitivities are not "
-                      f"in the sample), FP64 NumPy, {workers} processes, wall {wall:.1f} s"}
+            "est_solve_s": est,
+            "sample": f"{workers} processes in parallel, each: simulation of {n_sim} outer paths "
+                      f"x n_b={w.n_b} ({t_sim:.1f} s), one BaseAlg epoch on {n_rows} rows of one "
+                      f"date ({t_reg:.1f} s), CVA_0 of {n_sens} sensitivity paths ({t_sens:.1f} s); "
+                      f"scaled to M={w.M} paths, {dates} dates x {wr.mlp.epochs} epochs x {w.M} rows "
+                      f"and 2x{n_par} CVA_0 evaluations on {ws.M} paths; FP64 NumPy, one thread "
+                      f"per process, wall {wall:.1f} s"}
 
 
 # ------------------------------------------------------------------------------- plain FP32
@@ -173,7 +230,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--sim-only", action="store_true", help="time the simulation stages only")
-    ap.add_argument("--cpu-paths-per-worker", type=int, default=96)
+    ap.add_argument("--cpu-sim-paths", type=int, default=1280, help="oracle paths per process")
+    ap.add_argument("--cpu-rows", type=int, default=65536, help="oracle regression rows per process")
+    ap.add_argument("--cpu-sens-paths", type=int, default=384, help="oracle CVA_0 paths per process")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy first (scale of the FETCH/WRITE counters)")
     ap.add_argument("--plain-dates", type=int, default=2)
     args = ap.parse_args()
 
@@ -191,7 +252,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1))
-        cpu = cpu_baseline(w, name, kw, args.cpu_paths_per_worker, workers)
+        cpu = cpu_baseline(w, name, kw, workers, args.cpu_sim_paths, args.cpu_rows, args.cpu_sens_paths)
         print(f"# cpu baseline: {cpu['value']:.4g} path-steps/s ({cpu['sample']})",
               file=sys.stderr, flush=True)
 
@@ -199,6 +260,13 @@ def main():
     from paper_2211_17005_amd import hsim
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel are 1 GiB each
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prec = hsim.HSIM_FP32
     M, n1, C = w.M, w.grid.n_dates + 1, w.market.n_cpty
     d = wl.n_features(w)
@@ -289,7 +357,8 @@ def main():
         mlp_roof = {"bound": "mfma", "kernel": "mlp_train_kernel<128,3> (+ stats)",
                     "achieved": fl / (stage_ms["regression"] / 1e3) / 1e12,
                     "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s",
-                    "frac": fl / (stage_ms["regression"] / 1e3) / BF16_PEAK, "traffic": None}
+                    "frac": fl / (stage_ms["regression"] / 1e3) / BF16_PEAK,
+                    "traffic": profiled_traffic("mlp_train_kernel", "regress.hip")}
         if stage_ms["regression"] > stage_ms["outer"]:
             roof = mlp_roof
 
