@@ -220,6 +220,31 @@ def plain_regression_fp32(X, Y, mlp, dates, seed):
     torch.cuda.synchronize()
 
 
+# ------------------------------------------------------------------------------- sweep
+def oversim_sweep(hsim, torch, M: int, reps: int = 3):
+    """Batched oversimulation: the plain-case market at M outer paths, blocks of 64 paths with
+    n_b cycling through 1, 8, 64, 512, 1024, outer paths + inner draws + targets in one call
+    (the inner draws as one longest-first persistent launch).  Reports outer x inner
+    path-steps per second, sum_k n_b(k) * n_dates / time."""
+    w = wl.oversim_sweep(M=M)
+    nbb = w.extra["n_b_per_block"]
+    s = hsim.Solver(w, precision=hsim.HSIM_FP32, n_b_per_block=nbb, block_paths=64)
+    s.inner_defaults_cva(want_features=False)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        s.inner_defaults_cva(want_features=False)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / reps
+    nb_paths = np.repeat(nbb, 64)[:M].astype(np.float64)
+    steps = float(nb_paths.sum()) * w.grid.n_dates
+    return {"workload": w.name, "M": M, "levels": list(wl.OVERSIM_LEVELS), "block_paths": 64,
+            "ms_per_call": ms, "path_steps_per_s": steps / (ms / 1e3), "dtype": "f32 (f64 integrals)"}
+
+
 # ------------------------------------------------------------------------------- GPU step
 def main():
     ap = argparse.ArgumentParser()
@@ -233,6 +258,9 @@ def main():
     ap.add_argument("--cpu-sim-paths", type=int, default=1280, help="oracle paths per process")
     ap.add_argument("--cpu-rows", type=int, default=65536, help="oracle regression rows per process")
     ap.add_argument("--cpu-sens-paths", type=int, default=384, help="oracle CVA_0 paths per process")
+    ap.add_argument("--team", type=int, default=0, help="workgroups per date (0: autotuned)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the uneven-n_b sweep line")
+    ap.add_argument("--sweep-M", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (scale of the FETCH/WRITE counters)")
     ap.add_argument("--plain-dates", type=int, default=2)
@@ -291,6 +319,17 @@ def main():
 
     dates = list(range(1, w.grid.n_dates + 1))
     cfg = hsim.mlp_cfg(wr.mlp, d, M)
+    # team size (workgroups per date) from the autotuner's cache, timed once if absent; the
+    # tuning fit runs on the simulated features of a first, untimed simulation
+    hsim.check(L.hsim_outer_paths(by(km.struct), by(kp.struct), by(g), w.seed, 0, M, prec, fm,
+                                  P(feats), P(I), P(Lam), P(D), None, hsim._stream()))
+    hsim.check(L.hsim_inner_defaults(by(g), C, w.seed, 0, M, w.n_b, None, 64, P(Lam), P(cnt),
+                                     None, 0, hsim._stream()))
+    hsim.check(L.hsim_targets_cva(by(g), C, M, w.n_b, None, 64, prec, P(I), P(D), P(cnt),
+                                  P(T), P(cva0), P(ws), wsb, hsim._stream()))
+    if not args.sim_only:
+        from paper_2211_17005_amd import autotune
+        cfg.team = args.team if args.team > 0 else autotune.regression_team(cfg, dates, feats, T, seed=w.seed)
     rec = hsim.record_floats(cfg)
     model = torch.zeros((len(dates), rec), dtype=torch.float32, device="cuda")
     mws = L.cva_regress_workspace_bytes(by(cfg), len(dates), M)
@@ -389,6 +428,10 @@ def main():
                  f"{w.grid.n_dates - 1}", "sensitivities_s": fd_s,
                  "speedup_of_fast_form": plain_s / (ms_step / 1e3)}
 
+    sweep = None
+    if not args.sim_only and not args.no_sweep:
+        sweep = oversim_sweep(hsim, torch, args.sweep_M)
+
     rec_out = {
         "metric": "outer x inner path-steps/s of the whole CVA-with-sensitivities solve (1 GPU)",
         "value": value,
@@ -405,7 +448,7 @@ def main():
         "config": {"workload": w.name, "n_ccy": w.market.n_ccy, "n_cpty": C,
                    "n_swaps": w.portfolio.n_swaps, "n_dates": w.grid.n_dates,
                    "n_sub": w.grid.n_sub, "M": M, "n_b": w.n_b, "stages": stages,
-                   "regression": {"dates": len(dates), "hidden": wr.mlp.hidden,
+                   "regression": {"dates": len(dates), "hidden": wr.mlp.hidden, "team": int(cfg.team),
                                   "width": wr.mlp.width, "inputs": d, "batch": wr.mlp.batch,
                                   "epochs": wr.mlp.epochs},
                    "sensitivities": {"M": wa.M, "inputs": int(hsim.n_params(wa.market))}},
@@ -416,6 +459,7 @@ def main():
         "roofline_regression": mlp_roof,
         "cva0": cva0.item(),
         "plain_fp32": plain,
+        "oversim_sweep": sweep,
         "cpu_baseline": cpu,
         "wall_s": wall,
     }

@@ -162,9 +162,12 @@ int hsim_outer_paths(const hsim_market* market, const hsim_portfolio* book, cons
  *   j* = min{ j >= 1 : Lambda^c_j >= -log u }   (no default if none).
  * counts_dev [n+1][C][M] (int32) receives the number of draws defaulting at each date.
  * n_b(k) = n_b when n_b_per_block is NULL; otherwise path k uses
- * n_b_per_block[(k - path_begin) / block_paths] (host array of ceil(M/block_paths)
- * entries, block_paths a positive multiple of 64).  1 <= n_b(k) <= 2^24.
- * Needs hsim_workspace_bytes(HSIM_OP_INNER, ...) bytes of device workspace. */
+ * n_b_per_block[(k - path_begin) / block_paths] (device array of ceil(M/block_paths)
+ * entries, block_paths a positive multiple of 64).  1 <= n_b(k) <= 2^24.  Uneven n_b runs as
+ * one persistent launch that takes the 64-path tiles longest-first (tiles bucketed by
+ * floor(log2 n_b)); it needs hsim_workspace_bytes(HSIM_OP_INNER, ...) bytes of device
+ * workspace (HSIM_ENOWS otherwise).  Uniform n_b needs none (workspace may be NULL).  The
+ * counts do not depend on the schedule. */
 int hsim_inner_defaults(const hsim_grid* grid, int32_t n_cpty, uint64_t seed, int64_t path_begin,
                         int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
                         const double* Lambda_dev, int32_t* counts_dev, void* workspace_dev,

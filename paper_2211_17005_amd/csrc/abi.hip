@@ -423,8 +423,6 @@ int hsim_inner_defaults(const hsim_grid* g, int32_t n_cpty, uint64_t seed, int64
                         int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
                         const double* Lambda_dev, int32_t* counts_dev, void* workspace_dev, size_t ws_bytes,
                         void* stream) {
-  (void)workspace_dev;
-  (void)ws_bytes;
   int rc = check_grid(g);
   if (rc) return rc;
   if ((rc = check_paths(path_begin, M))) return rc;
@@ -445,6 +443,13 @@ int hsim_inner_defaults(const hsim_grid* g, int32_t n_cpty, uint64_t seed, int64
   a.block_paths = block_paths;
   a.Lam = Lambda_dev;
   a.counts = counts_dev;
+  a.order = nullptr;
+  if (n_b_per_block) {                   // uneven n_b: longest-first persistent schedule
+    const size_t need = align256(inner_order_bytes(M));
+    if (!workspace_dev || ws_bytes < need)
+      return fail(HSIM_ENOWS, "uneven n_b needs a workspace of %zu bytes (got %zu)", need, ws_bytes);
+    a.order = (int32_t*)workspace_dev;
+  }
   hipError_t e = launch_inner(a, (hipStream_t)stream);
   return e == hipSuccess ? HSIM_OK : device_error(e, "inner kernel launch");
 }
@@ -467,13 +472,17 @@ int hsim_targets_cva(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b,
                                    target_dev, cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream);
 }
 
+static size_t partial_bytes_of(int64_t M) {
+  return align256(sizeof(double) * (size_t)((M + kTargetBlock - 1) / kTargetBlock));
+}
+
 size_t hsim_workspace_bytes(int op, const hsim_market* m, const hsim_grid* g, int64_t M, int precision) {
   if (!g || M < 1) return 0;
   const size_t n1 = (size_t)g->n_dates + 1;
-  const size_t partial = align256(sizeof(double) * (size_t)((M + kTargetBlock - 1) / kTargetBlock));
+  const size_t partial = partial_bytes_of(M);
   switch (op) {
     case HSIM_OP_INNER:
-      return 0;
+      return align256(inner_order_bytes(M));
     case HSIM_OP_TARGETS:
       return partial;
     case HSIM_OP_FUSED: {
@@ -481,7 +490,8 @@ size_t hsim_workspace_bytes(int op, const hsim_market* m, const hsim_grid* g, in
       const size_t C = (size_t)m->n_cpty;
       const size_t rs = precision == HSIM_FP32 ? sizeof(float) : sizeof(double);
       return align256(n1 * M * sizeof(double)) + align256(n1 * C * M * sizeof(double)) +
-             align256(n1 * C * M * rs) + align256(n1 * C * M * sizeof(int32_t)) + partial;
+             align256(n1 * C * M * rs) + align256(n1 * C * M * sizeof(int32_t)) + partial +
+             align256(inner_order_bytes(M));
     }
     default:
       return hsim_adjoint_workspace(op, m, g, M, precision);
@@ -514,12 +524,14 @@ int hsim_inner_defaults_cva(const hsim_market* m, const hsim_portfolio* p, const
   int32_t* cnt = (int32_t*)w;
   w += align256(n1 * C * M * sizeof(int32_t));
   void* partial = w;
+  w += partial_bytes_of(M);
+  void* order = w;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = hsim_outer_paths(m, p, g, seed, path_begin, M, precision, feature_mode, features_dev, I, Lam, D,
                              nullptr, s)))
     return rc;
   if ((rc = hsim_inner_defaults(g, m->n_cpty, seed, path_begin, M, n_b, n_b_per_block, block_paths, Lam, cnt,
-                                nullptr, 0, s)))
+                                order, align256(inner_order_bytes(M)), s)))
     return rc;
   return hsim_targets_cva(g, m->n_cpty, M, n_b, n_b_per_block, block_paths, precision, I, D, cnt, target_dev,
                           cva0_dev, partial, hsim_workspace_bytes(HSIM_OP_TARGETS, m, g, M, precision), s);

@@ -203,17 +203,16 @@ void outer_kernel(const SimArgs<Real> a) {
 // ------------------------------------------------------------------------------------
 // inner default draws
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kInnerBlock) void inner_kernel(const InnerArgs a) {
-  extern __shared__ uint32_t lds[];
+// The draws of one tile of 64 paths (one lane per path).
+__device__ void inner_tile(const InnerArgs& a, uint32_t* lds, int64_t tile) {
   const int lane = threadIdx.x;
   const int n = a.n_dates;
   const int C = a.n_cpty;
   const int64_t M = a.M;
-  const int64_t kl = (int64_t)blockIdx.x * kInnerBlock + lane;
+  const int64_t kl = tile * kInnerBlock + lane;
   const bool valid = kl < M;
   const uint32_t k = a.path_begin + (uint32_t)kl;
-  const int nb = a.nb_block ? a.nb_block[((int64_t)blockIdx.x * kInnerBlock) / a.block_paths]
-                            : a.n_b;
+  const int nb = a.nb_block ? a.nb_block[(tile * kInnerBlock) / a.block_paths] : a.n_b;
   uint32_t* K = lds;                       // [(n+1)][64], column `lane` is private to it
   uint32_t* cnt = lds + (n + 1) * kInnerBlock;
 
@@ -252,6 +251,54 @@ __global__ __launch_bounds__(kInnerBlock) void inner_kernel(const InnerArgs a) {
       for (int j = 0; j <= n; ++j)
         a.counts[((int64_t)j * C + c) * M + kl] = (int32_t)cnt[j * kInnerBlock + lane];
     }
+  }
+}
+
+// One workgroup (one wave) per tile of 64 paths, or, with uneven n_b, a persistent grid that
+// takes the tiles longest-first from a work counter.  Every tile is computed the same way in
+// either schedule, so the counts do not depend on it.
+__global__ __launch_bounds__(kInnerBlock) void inner_kernel(const InnerArgs a) {
+  extern __shared__ uint32_t lds[];
+  if (a.order == nullptr) {
+    inner_tile(a, lds, blockIdx.x);
+    return;
+  }
+  const int64_t tiles = (a.M + kInnerBlock - 1) / kInnerBlock;
+  int32_t* queue = a.order + tiles;
+  for (;;) {
+    int t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(queue, 1);
+    t = __shfl(t, 0);
+    if (t >= tiles) break;
+    inner_tile(a, lds, a.order[t]);
+  }
+}
+
+// Longest-first order of the tiles of an uneven-n_b launch: tiles bucketed by floor(log2 n_b)
+// (largest first, tile order inside a bucket arbitrary); also clears the work counter.
+__global__ __launch_bounds__(1024) void inner_order_kernel(const int32_t* nb_block, int32_t block_paths,
+                                                           int64_t M, int32_t* order) {
+  __shared__ int cnt[32], off[32];
+  const int64_t tiles = (M + kInnerBlock - 1) / kInnerBlock;
+  if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < tiles; i += blockDim.x) {
+    const int nb = nb_block[(i * kInnerBlock) / block_paths];
+    atomicAdd(&cnt[__clz(nb > 0 ? nb : 1)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int b = 0; b < 32; ++b) {
+      off[b] = s;
+      s += cnt[b];
+    }
+    order[tiles] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < tiles; i += blockDim.x) {
+    const int nb = nb_block[(i * kInnerBlock) / block_paths];
+    order[atomicAdd(&off[__clz(nb > 0 ? nb : 1)], 1)] = (int32_t)i;
   }
 }
 
@@ -356,10 +403,25 @@ hipError_t launch_outer(const SimArgs<Real>& a, hipStream_t stream) {
   return hipErrorInvalidValue;
 }
 
+size_t inner_order_bytes(int64_t M) { return (size_t)((M + kInnerBlock - 1) / kInnerBlock + 1) * sizeof(int32_t); }
+
 hipError_t launch_inner(const InnerArgs& a, hipStream_t stream) {
-  const dim3 grid((unsigned)((a.M + kInnerBlock - 1) / kInnerBlock));
+  const int64_t tiles = (a.M + kInnerBlock - 1) / kInnerBlock;
   const size_t lds = (size_t)2 * (a.n_dates + 1) * kInnerBlock * sizeof(uint32_t);
-  hipLaunchKernelGGL(inner_kernel, grid, dim3(kInnerBlock), lds, stream, a);
+  unsigned grid = (unsigned)tiles;
+  if (a.order != nullptr) {
+    hipLaunchKernelGGL(inner_order_kernel, dim3(1), dim3(1024), 0, stream, a.nb_block, a.block_paths, a.M, a.order);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int dev = 0, ncu = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, inner_kernel, kInnerBlock, lds)) != hipSuccess)
+      return e;
+    const int64_t resident = (int64_t)ncu * (per_cu > 0 ? per_cu : 1);
+    grid = (unsigned)(tiles < resident ? tiles : resident);
+  }
+  hipLaunchKernelGGL(inner_kernel, dim3(grid), dim3(kInnerBlock), lds, stream, a);
   return hipGetLastError();
 }
 

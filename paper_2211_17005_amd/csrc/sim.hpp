@@ -60,6 +60,8 @@ struct InnerArgs {
   int32_t block_paths;
   const double* Lam;                 // [n+1][C][M]
   int32_t* counts;                   // [n+1][C][M]
+  int32_t* order;                    // uneven n_b: [tiles] tiles by decreasing n_b, then the
+                                     // work counter (workspace); null: one workgroup per tile
 };
 
 template <typename Real>
@@ -97,6 +99,8 @@ bool outer_supported(int n_ccy, int n_cpty);
 template <typename Real>
 hipError_t launch_outer(const SimArgs<Real>& a, hipStream_t stream);
 hipError_t launch_inner(const InnerArgs& a, hipStream_t stream);
+// Workspace of the longest-first schedule of an uneven-n_b inner launch over M paths.
+size_t inner_order_bytes(int64_t M);
 template <typename Real>
 hipError_t launch_targets(const TargetArgs<Real>& a, hipStream_t stream);
 hipError_t launch_philox_fill(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,

@@ -278,8 +278,11 @@ def inner_defaults(grid, n_cpty: int, seed: int, Lam, path_begin: int = 0, n_b: 
     counts = torch.empty((grid.n_dates + 1, n_cpty, M), dtype=torch.int32, device="cuda")
     nb, nbt, bp = _nb_args(n_b, n_b_per_block, block_paths)
     g = grid_struct(grid)
+    wsb = lib().hsim_workspace_bytes(OP_INNER, None, ctypes.byref(g), M, HSIM_FP32)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda") if nbt is not None else None
     check(lib().hsim_inner_defaults(ctypes.byref(g), n_cpty, seed, path_begin, M, nb, _dptr(nbt), bp,
-                                    _dptr(Lam), _dptr(counts), None, 0, _stream()))
+                                    _dptr(Lam), _dptr(counts), _dptr(ws), wsb if ws is not None else 0,
+                                    _stream()))
     torch.cuda.current_stream().synchronize() if nbt is not None else None
     return counts
 

@@ -141,3 +141,10 @@ def test_inner_rejects_bad_nb(hs, cpu_only):
                                         None, 0, None) == -2
     assert hs.lib().hsim_inner_defaults(ctypes.byref(g), 1, 0, 0, 64, 1, dummy, 48, dummy, dummy,
                                         None, 0, None) == -1
+    # uneven n_b runs longest-first from a work list kept in the workspace
+    need = hs.lib().hsim_workspace_bytes(hs.OP_INNER, None, ctypes.byref(g), 64, hs.HSIM_FP32)
+    assert need > 0
+    assert hs.lib().hsim_inner_defaults(ctypes.byref(g), 1, 0, 0, 64, 0, dummy, 64, dummy, dummy,
+                                        None, 0, None) == -3
+    assert hs.lib().hsim_inner_defaults(ctypes.byref(g), 1, 0, 0, 64, 0, dummy, 64, dummy, dummy,
+                                        dummy, need - 1, None) == -3
