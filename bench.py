@@ -78,10 +78,10 @@ def mlp_flops_per_date(d_in: int, width: int, hidden: int, M: int, epochs: int) 
     return epochs * M * (train + fwd) + M * (fwd + 2.0 * (U + 1) ** 2)
 
 
-def profiled_traffic(key: str, source: str):
-    """HBM bytes per launch of a kernel from the committed counter summaries (profiles/*.md),
-    or None when no summary covers it or its source file has changed since the counters were
-    taken (the summary records the sha256 of that file)."""
+def profiled_value(tag: str, key: str, source: str):
+    """A figure `tag key value` from the committed counter summaries (profiles/*.md), or None
+    when no summary holds it or the kernel's source file has changed since the counters were
+    taken (each summary records the sha256 of that file)."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2211_17005_amd", "csrc", source)
@@ -90,13 +90,18 @@ def profiled_traffic(key: str, source: str):
         value, sha = None, None
         for line in open(f):
             parts = line.split()
-            if len(parts) == 3 and parts[0] == "traffic_bytes_per_launch" and parts[1] == key:
+            if len(parts) == 3 and parts[0] == tag and parts[1] == key:
                 value = float(parts[2])
             if len(parts) == 2 and parts[0] == "source_sha256":
                 sha = parts[1]
         if value is not None and sha == digest:
             return value
     return None
+
+
+def profiled_traffic(key: str, source: str):
+    """HBM bytes per launch of a kernel (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return profiled_value("traffic_bytes_per_launch", key, source)
 
 
 # ------------------------------------------------------------------------------- CPU baseline
@@ -387,7 +392,8 @@ def main():
     outer_roof = {"bound": "alu", "kernel": "outer_kernel<float,10,8>",
                   "achieved": ops / (stage_ms["outer"] / 1e3) / 1e12,
                   "peak": VALU_PEAK_OPS / 1e12, "unit": "T VALU lane-ops/s",
-                  "frac": ops / (stage_ms["outer"] / 1e3) / VALU_PEAK_OPS, "traffic": None}
+                  "frac": ops / (stage_ms["outer"] / 1e3) / VALU_PEAK_OPS, "traffic": None,
+                  "valu_issue_utilization": profiled_value("valu_issue_utilization", "outer_kernel", "sim.hip")}
     roof = outer_roof
     mlp_roof = None
     if not args.sim_only:

@@ -196,6 +196,17 @@ int hsim_inner_defaults_cva(const hsim_market* market, const hsim_portfolio* boo
                             void* target_dev, double* cva0_dev, void* workspace_dev,
                             size_t ws_bytes, void* stream);
 
+/* Pilot moments of the oversimulation chooser (Section 3.3, Proposition p:heurisN).  For
+ * every date i and path k of T1_dev / T2_dev [n+1][M] (the n_b = 1 and n_b = 2 targets of
+ * one seed, float if FP32 else double; with the common random numbers of
+ * hsim_inner_defaults the first continuation of T2 is T1), the two pilot continuations
+ * xi1 = T1, xi2 = 2 T2 - T1 give the pointwise losses g = (xi - phi)^2 against pred_dev
+ * [n+1][M] (same type; NULL: phi = 0).  moments_dev [n+1][3] (double, device) receives
+ * E[g], E[g^2] (both continuations pooled) and E[g g'], reduced in FP64 in a fixed order;
+ * R = E[g g'] - E[g]^2 and Q = E[g^2] - E[g g'] give N*_i = sqrt(Q_i P / R_i) (e:optom). */
+int hsim_oversim_moments(const hsim_grid* grid, int64_t M, int precision, const void* T1_dev,
+                         const void* T2_dev, const void* pred_dev, double* moments_dev, void* stream);
+
 enum hsim_op { HSIM_OP_INNER = 1, HSIM_OP_TARGETS = 2, HSIM_OP_FUSED = 3, HSIM_OP_ADJOINT = 4 };
 
 /* Device workspace (bytes) an operation needs for M paths and the given market/grid. */

@@ -21,5 +21,8 @@ Parity status of the functions (what pins each one, besides the GPU path):
   regression (BaseAlg)   least-squares refit == numpy lstsq; h=0 fit == lstsq;
                          one Adam step == hand-derived update
   sensitivities (FD)     convergence in h; analytic derivative of a closed form
+  oversim (chooser)      R, Q recovered on a hierarchical sample of known variances; the
+                         variance law's minimiser over a brute-force grid equals N*; the
+                         proof's rearranged variance equals the direct one; l:ratio exact
 """
-from . import philox, closed_forms, model, inner, pipeline, regression, sensitivities  # noqa: F401
+from . import philox, closed_forms, model, inner, pipeline, regression, sensitivities, oversim  # noqa: F401

@@ -97,6 +97,7 @@ def lib():
                                            vp, u64, vp, vp, vp, sz, vp]),
         "cva_regress_predict": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32,
                                                vp, vp, vp, vp]),
+        "hsim_oversim_moments": (ctypes.c_int, [G_, i64, ctypes.c_int, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -305,6 +306,22 @@ def targets_cva(grid, n_cpty: int, I, D, counts, n_b: int = 1, n_b_per_block=Non
                                  _dptr(ws), wsb, _stream()))
     torch.cuda.current_stream().synchronize() if nbt is not None else None
     return T, cva0
+
+
+def oversim_moments(grid, T1, T2, pred=None, precision: int = HSIM_FP32):
+    """hsim_oversim_moments: [n+1][3] = E[g], E[g^2], E[g g'] of the two pilot continuations."""
+    import torch
+    M = T1.shape[-1]
+    R = _real(precision)
+    _expect(T1, R, (grid.n_dates + 1, M), "T1")
+    _expect(T2, R, (grid.n_dates + 1, M), "T2")
+    if pred is not None:
+        _expect(pred, R, (grid.n_dates + 1, M), "pred")
+    out = torch.empty((grid.n_dates + 1, 3), dtype=torch.float64, device="cuda")
+    g = grid_struct(grid)
+    check(lib().hsim_oversim_moments(ctypes.byref(g), M, precision, _dptr(T1), _dptr(T2), _dptr(pred),
+                                     _dptr(out), _stream()))
+    return out
 
 
 def workspace_bytes(op: int, w, M: int, precision: int) -> int:

@@ -1,0 +1,65 @@
+"""Choice of the oversimulation factor N and of the number of outer paths M for a budget
+(Section 3.3: Proposition p:heurisN, Heuristic heur:MN, cost ratio l:ratio), on the GPU.
+
+1. Pilot: the targets at n_b = 1 and n_b = 2 of one seed (common random numbers make the first
+   continuation of the n_b = 2 run the n_b = 1 run), reduced per date by hsim_oversim_moments
+   into R_i = Cov(g, g') and Q_i = E[Var(g | outer path)] of the pointwise loss
+   g = (xi - phi)^2 (phi = the given predictions, 0 before training).
+2. Cost ratio: P, the cost of one outer path in units of one inner continuation, from the
+   times of two fused simulations with the same M and n_b = N, N' (t / t' = (P + N) / (P + N')).
+3. N*_i = sqrt(Q_i P / R_i) at every date with R_i > 0; N = their mean (at least 1);
+   M = Psi / (N + P) for a budget of Psi inner-continuation units.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import hsim
+
+
+def _timed_solve(w, n_b: int, M: int, reps: int) -> float:
+    import torch
+    s = hsim.Solver(w.with_(n_b=int(n_b)), precision=hsim.HSIM_FP32, M=M)
+    s.inner_defaults_cva(want_features=False)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        s.inner_defaults_cva(want_features=False)
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / reps / 1e3
+
+
+def pilot(w, M: int, pred=None):
+    """R_i, Q_i of every date from the n_b = 1, 2 pilot on M outer paths (FP32 simulation)."""
+    T = []
+    for n_b in (1, 2):
+        s = hsim.Solver(w.with_(n_b=n_b), precision=hsim.HSIM_FP32, M=M)
+        s.inner_defaults_cva(want_features=False)
+        T.append(s.T.clone())
+    mom = hsim.oversim_moments(w.grid, T[0], T[1], pred).cpu().numpy()
+    R = mom[:, 2] - mom[:, 0] ** 2
+    Q = mom[:, 1] - mom[:, 2]
+    return R, Q
+
+
+def cost_ratio(w, M: int, n_b=(1, 64), reps: int = 3) -> float:
+    """P from the times of (M, N) and (M, N') (l:ratio)."""
+    N, Np = n_b
+    t, tp = _timed_solve(w, N, M, reps), _timed_solve(w, Np, M, reps)
+    return (tp * N - t * Np) / (t - tp)
+
+
+def choose(w, Psi: float, M_pilot: int = 1 << 16, pred=None, P=None) -> dict:
+    """Heuristic heur:MN for workload w and a budget Psi (in units of one inner continuation)."""
+    R, Q = pilot(w, M_pilot, pred)
+    if P is None:
+        P = cost_ratio(w, M_pilot)
+    ok = (R > 0.0) & (Q >= 0.0)
+    n_star = np.sqrt(Q[ok] * P / R[ok])
+    N = max(1.0, float(n_star.mean())) if n_star.size else 1.0
+    return {"N": N, "n_b": int(max(1, round(N))), "M": Psi / (N + P), "P": float(P),
+            "N_dates": n_star, "R": R, "Q": Q}
