@@ -320,9 +320,19 @@ __device__ __forceinline__ float store_chunk(const Smem<U, H>& S, const ChunkReg
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
-// Hidden layer L: A_L = relu(W_L A_{L-1} + b_L), BF16 into A(L).
+// Bit v set where h[v] != 0 (for h >= 0: where h[v] > 0), tested on the packed 16-bit words.
+__device__ __forceinline__ uint32_t nonzero_bits(const bf16x4& h) {
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 w = __builtin_bit_cast(u32x2, h);
+  return (uint32_t)((w.x & 0xFFFFu) != 0u) | ((uint32_t)((w.x >> 16) != 0u) << 1) |
+         ((uint32_t)((w.y & 0xFFFFu) != 0u) << 2) | ((uint32_t)((w.y >> 16) != 0u) << 3);
+}
+
+// Hidden layer L: A_L = relu(W_L A_{L-1} + b_L), BF16 into A(L).  Returns the lane's ReLU mask:
+// bit 4 (x BR + y) + v set when element v of its tile strip (x, y) is positive; the backward
+// pass produces dH_L in the same lanes and tile order, so the mask never goes through LDS.
 template <int U, int H, int L>
-__device__ void forward_layer(const Smem<U, H>& S, const Lanes& ln) {
+__device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln) {
   using B = Blk<U>;
   constexpr int K = Smem<U, H>::ldk(L), SWl = Smem<U, H>::lds(L);
   constexpr int SW = Smem<U, H>::SW;
@@ -351,6 +361,7 @@ __device__ void forward_layer(const Smem<U, H>& S, const Lanes& ln) {
       for (int y = 0; y < B::BR; ++y) acc[x][y] = mfma16(av[x], bv[y], acc[x][y]);
   }
   const float* b = S.bias(L);
+  uint32_t mask = 0u;
   float pf[B::BR];                      // last layer: this lane's part of f = A_H w_out
 #pragma unroll
   for (int y = 0; y < B::BR; ++y) pf[y] = 0.0f;
@@ -368,6 +379,7 @@ __device__ void forward_layer(const Smem<U, H>& S, const Lanes& ln) {
         h[v] = (__bf16)fmaxf(acc[x][y][v] + bb[v], 0.0f);
         if constexpr (L == H) pf[y] += (float)h[v] * wo[v];
       }
+      mask |= nonzero_bits(h) << (4 * (x * B::BR + y));
       *tile_strip(Aout, oo, SW, rb * B::BR + y, ob * B::BO + x) = h;
     }
   }
@@ -381,6 +393,7 @@ __device__ void forward_layer(const Smem<U, H>& S, const Lanes& ln) {
     }
   }
   __syncthreads();
+  return mask;
 }
 
 // f of row r (after the forward): the out-block partials in a fixed order, plus b_out.
@@ -392,12 +405,24 @@ __device__ __forceinline__ float output_of_row(const Smem<U, H>& S, int r) {
   return f + S.scal()[0];
 }
 
+// ReLU masks of the hidden layers below the last (layer l in m[l - 1]).
+struct Masks {
+  uint32_t m[2];
+};
+
 template <int U, int H>
-__device__ void forward(const Smem<U, H>& S, const Lanes& ln) {
-  forward_layer<U, H, 1>(S, ln);
-  if constexpr (H >= 2) forward_layer<U, H, 2>(S, ln);
+__device__ Masks forward(const Smem<U, H>& S, const Lanes& ln) {
+  Masks k{{0u, 0u}};
+  k.m[0] = forward_layer<U, H, 1>(S, ln);
+  if constexpr (H >= 2) k.m[1] = forward_layer<U, H, 2>(S, ln);
   if constexpr (H >= 3) forward_layer<U, H, 3>(S, ln);
+  return k;
 }
+
+// LDS buffer holding dZ_l in the backward pass.  dZ_H overwrites A_H and dZ_{H-1} overwrites
+// A_{H-1} (after a barrier); every lower dZ_l goes to the buffer of A_{l+2}, whose gradient was
+// consumed two layers up, so it is written in the same phase as the products that read A_l.
+constexpr int dz_buf(int l, int H) { return l >= H - 1 ? l : l + 2; }
 
 // ------------------------------------------------------------------------------------------
 // backward
@@ -410,7 +435,7 @@ __device__ void accumulate_dw(const Smem<U, H>& S, const Lanes& ln, f32x4* accW)
   const int wave = wave_id(), lane = lane_id();
   const int ib = wave % M::NIB, ob = wave / M::NIB;
   if (ob >= M::NOB) return;
-  const __bf16* dZ = S.A(L);
+  const __bf16* dZ = S.A(dz_buf(L, H));
   const __bf16* Ain = S.A(L - 1);
   constexpr int SW = Smem<U, H>::SW, SWin = Smem<U, H>::lds(L);
   const LaneOffsets& oz = ln.o;
@@ -455,7 +480,7 @@ __device__ void backprop_compute(const Smem<U, H>& S, const Lanes& ln, f32x4 (&d
   const int ob = wave % B::NOB, rb = wave / B::NOB;
   const LaneOffsets& o = ln.o;
   const __bf16* W = S.W(L);
-  const __bf16* dZ = S.A(L);
+  const __bf16* dZ = S.A(dz_buf(L, H));
 #pragma unroll
   for (int x = 0; x < B::BO; ++x)
 #pragma unroll
@@ -474,38 +499,39 @@ __device__ void backprop_compute(const Smem<U, H>& S, const Lanes& ln, f32x4 (&d
   }
 }
 
-// dZ_{L-1} = dH_{L-1} masked by the ReLU of layer L-1, written over A(L-1).
+// dZ_{L-1} = dH_{L-1} masked by the ReLU of layer L-1 (the forward pass's mask bits of these
+// lanes), into its backward buffer.
 template <int U, int H, int L>
-__device__ void backprop_store(const Smem<U, H>& S, const Lanes& ln, const f32x4 (&dh)[Blk<U>::BO][Blk<U>::BR]) {
+__device__ void backprop_store(const Smem<U, H>& S, const Lanes& ln, const f32x4 (&dh)[Blk<U>::BO][Blk<U>::BR],
+                               uint32_t mask) {
   using B = Blk<U>;
   constexpr int SW = Smem<U, H>::SW;
   const int wave = wave_id();
   const int ob = wave % B::NOB, rb = wave / B::NOB;
   const LaneOffsets& o = ln.o;
-  __bf16* Ap = S.A(L - 1);
+  __bf16* dst = S.A(dz_buf(L - 1, H));
 #pragma unroll
   for (int x = 0; x < B::BO; ++x)
 #pragma unroll
     for (int y = 0; y < B::BR; ++y) {
-      bf16x4* p = tile_strip(Ap, o, SW, rb * B::BR + y, ob * B::BO + x);
-      const bf16x4 a = *p;
       bf16x4 z;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) z[v] = (float)a[v] > 0.0f ? (__bf16)dh[x][y][v] : (__bf16)0.0f;
-      *p = z;
+      for (int v = 0; v < 4; ++v)
+        z[v] = (mask >> (4 * (x * B::BR + y) + v)) & 1u ? (__bf16)dh[x][y][v] : (__bf16)0.0f;
+      *tile_strip(dst, o, SW, rb * B::BR + y, ob * B::BO + x) = z;
     }
 }
 
 template <int U, int H, int L>
-__device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, f32x4* accW) {
+__device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW) {
   accumulate_dw<U, H, L>(S, ln, accW);
   if constexpr (L > 1) {
     f32x4 dh[Blk<U>::BO][Blk<U>::BR];
     backprop_compute<U, H, L>(S, ln, dh);
-    __syncthreads();                    // every read of A(L-1) and dZ_L is done
-    backprop_store<U, H, L>(S, ln, dh);
+    if constexpr (dz_buf(L - 1, H) == L - 1) __syncthreads();   // in place: A(L-1) is read above
+    backprop_store<U, H, L>(S, ln, dh, mk.m[L - 2]);
     __syncthreads();
-    layer_backward<U, H, L - 1>(S, ln, accW);
+    layer_backward<U, H, L - 1>(S, ln, mk, accW);
   } else {
     __syncthreads();
   }
@@ -513,7 +539,7 @@ __device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, f32x4* accW
 
 // Gradients of one chunk, accumulated over the batch.  dff of the chunk's rows is in LDS.
 template <int U, int H>
-__device__ void backward(const Smem<U, H>& S, const Lanes& ln, f32x4* accW) {
+__device__ void backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW) {
   const int tid = opaque_tid();
   // dZ_H = [A_H > 0] dff w_out^T in place, and the partial sums of dff^T A_H (output weights)
   {
@@ -547,7 +573,7 @@ __device__ void backward(const Smem<U, H>& S, const Lanes& ln, f32x4* accW) {
     for (int q = 0; q < RS; ++q) s += part[q * U + tid];
     S.gwout()[tid] = s;
   }
-  layer_backward<U, H, H>(S, ln, accW);
+  layer_backward<U, H, H>(S, ln, mk, accW);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1017,7 +1043,7 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
         const float y = store_chunk<U, H>(S, c, n);
         if (r0 + cstride < b1) c = feed.load(r0 + cstride, (int)min((int64_t)R, b1 - r0 - cstride));
         __syncthreads();
-        forward<U, H>(S, ln);
+        const Masks mk = forward<U, H>(S, ln);
         if (opaque_tid() < R) {             // wave 0: one row per lane
           const int r = opaque_tid();
           const float f = output_of_row<U, H>(S, r);
@@ -1032,7 +1058,7 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
           }
         }
         __syncthreads();
-        backward<U, H>(S, ln, accW);
+        backward<U, H>(S, ln, mk, accW);
       }
       p1 *= a.beta1;
       p2 *= a.beta2;
