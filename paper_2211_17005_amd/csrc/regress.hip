@@ -301,14 +301,14 @@ struct Feeder {
 // Standardised inputs (BF16) into A(0); returns the scaled target of row t held by thread t < 64
 // (and stores it in ybuf for the refit).
 template <int U, int H>
-__device__ __forceinline__ float store_chunk(const Smem<U, H>& S, const ChunkRegs& c, int n) {
+__device__ __forceinline__ float store_chunk(const Smem<U, H>& S, const ChunkRegs& c, int n, __bf16* dst = nullptr) {
   const int t = opaque_tid(), r = t % kMlpRows, f0 = 4 * (t / kMlpRows);
   const f32x4 mean = *(const f32x4*)&S.xmean()[f0];
   const f32x4 inv = *(const f32x4*)&S.xinv()[f0];
   bf16x4 v;
 #pragma unroll
   for (int q = 0; q < 4; ++q) v[q] = (__bf16)(r < n ? (c.x[q] - mean[q]) * inv[q] : 0.0f);
-  *(bf16x4*)&S.A(0)[lidx(r, f0, S.SW0)] = v;
+  *(bf16x4*)&(dst ? dst : S.A(0))[lidx(r, f0, S.SW0)] = v;
   float y = 0.0f;
   if (t < kMlpRows) {
     y = t < n ? c.y / S.scal()[4] : 0.0f;
@@ -331,8 +331,12 @@ __device__ __forceinline__ uint32_t nonzero_bits(const bf16x4& h) {
 // Hidden layer L: A_L = relu(W_L A_{L-1} + b_L), BF16 into A(L).  Returns the lane's ReLU mask:
 // bit 4 (x BR + y) + v set when element v of its tile strip (x, y) is positive; the backward
 // pass produces dH_L in the same lanes and tile order, so the mask never goes through LDS.
-template <int U, int H, int L>
-__device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln) {
+//
+// a0 is the input buffer of layer 1; with kKeep false the last layer does not store A_H (only the
+// output partials) and leaves its closing barrier to the caller (the scans stage the next
+// chunk's inputs in that phase).
+template <int U, int H, int L, bool kKeep = true>
+__device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __bf16* a0) {
   using B = Blk<U>;
   constexpr int K = Smem<U, H>::ldk(L), SWl = Smem<U, H>::lds(L);
   constexpr int SW = Smem<U, H>::SW;
@@ -341,7 +345,7 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln) {
   const LaneOffsets& oi = L == 1 ? ln.o0 : ln.o;
   const LaneOffsets& oo = ln.o;
   const __bf16* W = S.W(L);
-  const __bf16* Ain = S.A(L - 1);
+  const __bf16* Ain = L == 1 ? a0 : S.A(L - 1);
   __bf16* Aout = S.A(L);
   f32x4 acc[B::BO][B::BR];
 #pragma unroll
@@ -380,7 +384,7 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln) {
         if constexpr (L == H) pf[y] += (float)h[v] * wo[v];
       }
       mask |= nonzero_bits(h) << (4 * (x * B::BR + y));
-      *tile_strip(Aout, oo, SW, rb * B::BR + y, ob * B::BO + x) = h;
+      if (kKeep || L < H) *tile_strip(Aout, oo, SW, rb * B::BR + y, ob * B::BO + x) = h;
     }
   }
   if constexpr (L == H) {
@@ -392,7 +396,7 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln) {
       if (lane < 16) S.fpart()[ob * kMlpRows + 16 * (rb * B::BR + y) + lane] = pf[y];
     }
   }
-  __syncthreads();
+  if (kKeep || L < H) __syncthreads();
   return mask;
 }
 
@@ -413,10 +417,27 @@ struct Masks {
 template <int U, int H>
 __device__ Masks forward(const Smem<U, H>& S, const Lanes& ln) {
   Masks k{{0u, 0u}};
-  k.m[0] = forward_layer<U, H, 1>(S, ln);
-  if constexpr (H >= 2) k.m[1] = forward_layer<U, H, 2>(S, ln);
-  if constexpr (H >= 3) forward_layer<U, H, 3>(S, ln);
+  k.m[0] = forward_layer<U, H, 1>(S, ln, S.A(0));
+  if constexpr (H >= 2) k.m[1] = forward_layer<U, H, 2>(S, ln, S.A(0));
+  if constexpr (H >= 3) forward_layer<U, H, 3>(S, ln, S.A(0));
   return k;
+}
+
+// Forward of a scan over the sample (loss, prediction): inputs from a0, A_H not kept, the last
+// layer's barrier left to the caller.
+template <int U, int H>
+__device__ void forward_scan(const Smem<U, H>& S, const Lanes& ln, const __bf16* a0) {
+  forward_layer<U, H, 1, false>(S, ln, a0);
+  if constexpr (H >= 2) forward_layer<U, H, 2, false>(S, ln, a0);
+  if constexpr (H >= 3) forward_layer<U, H, 3, false>(S, ln, a0);
+}
+
+// Input buffers of a scan: A(0) and the buffer of A_H (unused by a scan), alternating by chunk,
+// so the next chunk is staged while the current one is in its last layer.
+template <int U, int H>
+__device__ __forceinline__ __bf16* scan_buf(const Smem<U, H>& S, int parity) {
+  static_assert(Smem<U, H>::SW >= Smem<U, H>::SW0, "input rows fit in a hidden-layer buffer");
+  return parity ? S.A(H) : S.A(0);
 }
 
 // LDS buffer holding dZ_l in the backward pass.  dZ_H overwrites A_H and dZ_{H-1} overwrites
@@ -768,18 +789,29 @@ __device__ float full_loss(const Smem<U, H>& S, const Lanes& ln, const Feeder& f
   const int64_t stride = (int64_t)R * tm.G;
   double e = 0.0;
   const int64_t first = (int64_t)R * tm.member;
-  ChunkRegs c = feed.load(first, (int)max((int64_t)0, min((int64_t)R, a.M - first)));
+  auto rows = [&](int64_t r0) { return (int)max((int64_t)0, min((int64_t)R, a.M - r0)); };
+  ChunkRegs c = feed.load(first, rows(first));
+  float y = store_chunk<U, H>(S, c, rows(first), scan_buf(S, 0));
+  c = feed.load(first + stride, rows(first + stride));
+  __syncthreads();
+  int parity = 0;
   for (int64_t r0 = first; r0 < a.M; r0 += stride) {
-    const int n = (int)min((int64_t)R, a.M - r0);
-    const float y = store_chunk<U, H>(S, c, n);
-    if (r0 + stride < a.M) c = feed.load(r0 + stride, (int)min((int64_t)R, a.M - r0 - stride));
+    const int n = rows(r0);
+    float y_next = 0.0f;
+    forward_scan<U, H>(S, ln, scan_buf(S, parity));
+    // the next chunk goes into the other buffer in this chunk's last-layer phase
+    if (r0 + stride < a.M) {
+      y_next = store_chunk<U, H>(S, c, rows(r0 + stride), scan_buf(S, parity ^ 1));
+      c = feed.load(r0 + 2 * stride, rows(r0 + 2 * stride));
+    }
     __syncthreads();
-    forward<U, H>(S, ln);
     const int t = opaque_tid();
     if (t < n) {
       const float d = fmaxf(output_of_row<U, H>(S, t), 0.0f) + S.scal()[1] - y;
       e += (double)d * (double)d;
     }
+    y = y_next;
+    parity ^= 1;
   }
   __syncthreads();
   double* red = (double*)S.red();
@@ -1131,15 +1163,23 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs 
   const float ysc = rec[L.yscale_off()];
   const Lanes ln(Smem<U, H>::SW0, Smem<U, H>::SW);
   const Feeder feed(a, date);
-  ChunkRegs c = feed.load(k0, (int)min((int64_t)R, k1 - k0));
+  auto rows = [&](int64_t r0) { return (int)max((int64_t)0, min((int64_t)R, k1 - r0)); };
+  ChunkRegs c = feed.load(k0, rows(k0));
+  store_chunk<U, H>(S, c, rows(k0), scan_buf(S, 0));
+  c = feed.load(k0 + R, rows(k0 + R));
+  __syncthreads();
+  int parity = 0;
   for (int64_t r0 = k0; r0 < k1; r0 += R) {
-    const int n = (int)min((int64_t)R, k1 - r0);
-    store_chunk<U, H>(S, c, n);
-    if (r0 + R < k1) c = feed.load(r0 + R, (int)min((int64_t)R, k1 - r0 - R));
+    const int n = rows(r0);
+    forward_scan<U, H>(S, ln, scan_buf(S, parity));
+    if (r0 + R < k1) {
+      store_chunk<U, H>(S, c, rows(r0 + R), scan_buf(S, parity ^ 1));
+      c = feed.load(r0 + 2 * R, rows(r0 + 2 * R));
+    }
     __syncthreads();
-    forward<U, H>(S, ln);
     const int t = opaque_tid();
     if (t < n) out[(int64_t)job * a.M + r0 + t] = (fmaxf(output_of_row<U, H>(S, t), 0.0f) + S.scal()[1]) * ysc;
+    parity ^= 1;
   }
 }
 
