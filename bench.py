@@ -6,7 +6,8 @@ sub-steps over 10y, FP32 simulation with FP64 integrals):
   1. M = 2^17 outer paths + pricing -> n_b = 128 inner default draws -> targets and CVA_0;
   2. NN^+ regression of the targets at all 100 dates in one persistent launch (3 x 128 ReLU,
      29 inputs, BF16 on the matrix cores, batch 8192, 50 epochs);
-  3. CVA_0 sensitivities to the 90 model inputs by the tangent/adjoint sweeps (M = 2^16).
+  3. CVA_0 sensitivities to the 90 model inputs by the tangent/adjoint sweeps on the first
+     M = 2^16 of those paths (their forward states taken from step 1).
 The metric is outer x inner path-steps per second of the whole step:
 M * n_b * n_dates / (seconds per step).
 
@@ -364,7 +365,9 @@ def main():
                                      P(feats), P(T), w.seed, P(model), None, P(mws_t), mws,
                                      hsim._stream()))
         mark(4)
-        adj()
+        # sensitivities on the first 2^16 of the paths just simulated (same market and seed): the
+        # adjoint reads their forward states instead of simulating them again
+        adj.from_forward(feats, I, Lam, D)
         mark(5)
 
     for _ in range(args.warmup):

@@ -293,6 +293,20 @@ int cva_adjoint(const hsim_market* market, const hsim_portfolio* book, const hsi
                 int64_t path_begin, int64_t M, double* cva0_dev, double* grad_dev, void* workspace_dev,
                 size_t ws_bytes, void* stream);
 
+/* cva_adjoint on outer paths that an earlier hsim_outer_paths call (same market, book, grid and
+ * seed, FP32) has already simulated: their forward outputs are read from features_dev
+ * [n+1][n_feat][ld] (the market factors first: any feature mode), I_dev [n+1][ld],
+ * Lambda_dev [n+1][C][ld] and D_dev [n+1][C][ld], paths path_begin .. path_begin + M - 1 at
+ * columns 0 .. M - 1 (ld >= M; e.g. the first M paths of a larger simulation), and no forward
+ * pass is run.  The results equal cva_adjoint's.  The workspace (per-path gradient rows) may be
+ * smaller than hsim_workspace_bytes(HSIM_OP_ADJOINT, ...): it needs (hsim_n_params + 1) * M
+ * doubles, 256-byte aligned. */
+int cva_adjoint_forward(const hsim_market* market, const hsim_portfolio* book, const hsim_grid* grid,
+                        uint64_t seed, int64_t path_begin, int64_t M, int64_t ld, int32_t n_feat,
+                        const float* features_dev, const double* I_dev, const double* Lambda_dev,
+                        const float* D_dev, double* cva0_dev, double* grad_dev, void* workspace_dev,
+                        size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -104,7 +104,7 @@ void credit_kernel(const AdjArgs a) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double S = exp(-Lam[c]);
-      const double D = (double)s.D[((int64_t)jd * NC + c) * M + kl];
+      const double D = (double)s.D[((int64_t)jd * NC + c) * a.ld + kl];
       J += D * (Sprev[c] - S);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -194,8 +194,8 @@ __device__ void pricing_adjoint(const AdjArgs& a, int i, int64_t kl, const float
   double Jd = 0.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const double S1 = exp(-a.sim.Lam[((int64_t)(i - 1) * NC + c) * M + kl]);
-    const double S2 = exp(-a.sim.Lam[((int64_t)i * NC + c) * M + kl]);
+    const double S1 = exp(-a.sim.Lam[((int64_t)(i - 1) * NC + c) * a.ld + kl]);
+    const double S2 = exp(-a.sim.Lam[((int64_t)i * NC + c) * a.ld + kl]);
     const double p = S1 - S2;
     const double pos = mtm[c] > 0.0f ? (double)mtm[c] : 0.0;
     Jd += p * (double)s.lgd[c] * beta * pos;
@@ -290,15 +290,15 @@ void market_adjoint_kernel(const AdjArgs a) {
   const float* Fe = s.features;
   auto load_state = [&](int i, float* r, float* x) {
 #pragma unroll
-    for (int e = 0; e < NE; ++e) r[e] = Fe[((int64_t)i * nf + e) * M + kl];
+    for (int e = 0; e < NE; ++e) r[e] = Fe[((int64_t)i * nf + e) * a.ld + kl];
 #pragma unroll
-    for (int e = 1; e < NE; ++e) x[e - 1] = Fe[((int64_t)i * nf + NE + e - 1) * M + kl];
+    for (int e = 1; e < NE; ++e) x[e - 1] = Fe[((int64_t)i * nf + NE + e - 1) * a.ld + kl];
   };
 
   for (int i = n; i >= 1; --i) {
     float r[NE], x[NE > 1 ? NE - 1 : 1], rlr[NE], xd[NE > 1 ? NE - 1 : 1];
     load_state(i, r, x);
-    const double Ii = s.I[(int64_t)i * M + kl];
+    const double Ii = s.I[(int64_t)i * a.ld + kl];
     const int lr = (i % q == 0) ? i - q : (i / q) * q;
     load_state(lr, rlr, xd);
     if (i % q == 0) {                      // later dates priced off r at this reset date

@@ -31,6 +31,7 @@ struct AdjParams {
 
 struct AdjArgs {
   SimArgs<float> sim;            // tables and the forward outputs (features, I, Lam, D)
+  int64_t ld;                    // row stride of the forward outputs (>= sim.M)
   const float* dlnA_da;          // [n_ccy][n+1] derivatives of the Vasicek coefficient tables
   const float* dlnA_db;
   const float* dlnA_ds;

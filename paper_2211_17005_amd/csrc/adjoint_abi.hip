@@ -60,22 +60,49 @@ int hsim_n_params(const hsim_market* m) {
   return AdjParams::make(m->n_ccy, m->n_cpty).n_params;
 }
 
-int cva_adjoint(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed, int64_t path_begin,
-                int64_t M, double* cva0_dev, double* grad_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Forward outputs handed in by the caller (features with the market factors first, row stride ld).
+struct Forward {
+  const float* features;
+  int32_t n_feat;
+  const double* I;
+  const double* Lam;
+  const float* D;
+  int64_t ld;
+};
+
+int run_adjoint(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed, int64_t path_begin,
+                int64_t M, const Forward* fw, double* cva0_dev, double* grad_dev, void* workspace_dev,
+                size_t ws_bytes, void* stream) {
   AdjArgs a;
   memset(&a, 0, sizeof(a));
   int rc = build_sim_args<float>(m, p, g, seed, path_begin, M, HSIM_FEAT_FACTORS, a.sim);
   if (rc) return rc;
   if (!cva0_dev) return fail(HSIM_EINVAL, "cva0 must not be NULL");
   const AdjLayout L = adj_layout(m, g, M);
-  if (!workspace_dev || ws_bytes < L.total) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  const size_t need = fw ? L.total - L.grad : L.total;
+  if (!workspace_dev || ws_bytes < need) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, need);
   char* w = (char*)workspace_dev;
-  a.sim.features = (float*)(w + L.feat);
-  a.sim.I = (double*)(w + L.I);
-  a.sim.Lam = (double*)(w + L.Lam);
-  a.sim.D = (float*)(w + L.D);
+  if (fw) {
+    a.sim.features = const_cast<float*>(fw->features);
+    a.sim.n_feat = fw->n_feat;
+    a.sim.I = const_cast<double*>(fw->I);
+    a.sim.Lam = const_cast<double*>(fw->Lam);
+    a.sim.D = const_cast<float*>(fw->D);
+    a.ld = fw->ld;
+    a.grad_path = (double*)w;
+  } else {
+    a.sim.features = (float*)(w + L.feat);
+    a.sim.I = (double*)(w + L.I);
+    a.sim.Lam = (double*)(w + L.Lam);
+    a.sim.D = (float*)(w + L.D);
+    a.ld = M;
+    a.grad_path = (double*)(w + L.grad);
+  }
   a.sim.MtM = nullptr;
-  a.grad_path = (double*)(w + L.grad);
   a.grad_out = grad_dev;
   a.cva0_out = cva0_dev;
   const int NE = m->n_ccy, NC = m->n_cpty, n = g->n_dates;
@@ -119,11 +146,36 @@ int cva_adjoint(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* 
   a.dlnA_ds = a.dlnA_db + nz;
   a.dB_da = a.dlnA_ds + nz;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_outer<float>(a.sim, s);
-  if (e != hipSuccess) return device_error(e, "forward simulation launch");
+  hipError_t e = hipSuccess;
+  if (!fw) {
+    e = launch_outer<float>(a.sim, s);
+    if (e != hipSuccess) return device_error(e, "forward simulation launch");
+  }
   e = launch_adjoint(a, grad_dev != nullptr, s);
   if (e != hipSuccess) return device_error(e, "adjoint launch");
   return HSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cva_adjoint(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed, int64_t path_begin,
+                int64_t M, double* cva0_dev, double* grad_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+  return run_adjoint(m, p, g, seed, path_begin, M, nullptr, cva0_dev, grad_dev, workspace_dev, ws_bytes, stream);
+}
+
+int cva_adjoint_forward(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed,
+                        int64_t path_begin, int64_t M, int64_t ld, int32_t n_feat, const float* features_dev,
+                        const double* I_dev, const double* Lambda_dev, const float* D_dev, double* cva0_dev,
+                        double* grad_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+  if (!m || !g) return fail(HSIM_EINVAL, "market and grid must not be NULL");
+  if (ld < M) return fail(HSIM_EINVAL, "ld=%lld < M=%lld", (long long)ld, (long long)M);
+  if (n_feat < 2 * m->n_ccy - 1 + m->n_cpty)
+    return fail(HSIM_EINVAL, "n_feat=%d: the market factors (%d) must come first", n_feat, 2 * m->n_ccy - 1 + m->n_cpty);
+  if (!features_dev || !I_dev || !Lambda_dev || !D_dev) return fail(HSIM_EINVAL, "forward outputs must not be NULL");
+  const Forward fw{features_dev, n_feat, I_dev, Lambda_dev, D_dev, ld};
+  return run_adjoint(m, p, g, seed, path_begin, M, &fw, cva0_dev, grad_dev, workspace_dev, ws_bytes, stream);
 }
 
 }  // extern "C"

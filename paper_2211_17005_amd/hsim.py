@@ -98,6 +98,8 @@ def lib():
         "cva_regress_predict": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32,
                                                vp, vp, vp, vp]),
         "hsim_oversim_moments": (ctypes.c_int, [G_, i64, ctypes.c_int, vp, vp, vp, vp, vp]),
+        "cva_adjoint_forward": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i64, i32, vp, vp, vp, vp, vp,
+                                               vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -448,6 +450,19 @@ class Adjoint:
         self.P = n_params(w.market)
         self.cva0 = torch.empty(1, dtype=torch.float64, device="cuda")
         self.grad = torch.empty(self.P, dtype=torch.float64, device="cuda")
+
+    def from_forward(self, features, I, Lam, D, path_begin: int = 0, with_grad: bool = True):
+        """cva_adjoint_forward on the first self.M paths of an earlier FP32 simulation of the same
+        workload (features [n+1][d][ld], I [n+1][ld], Lam and D [n+1][C][ld] device tensors)."""
+        km = market_struct(self.w.market)
+        ld = int(I.shape[-1])
+        check(lib().cva_adjoint_forward(ctypes.byref(km.struct), ctypes.byref(self.kp.struct),
+                                        ctypes.byref(self.g), self.w.seed, path_begin, self.M, ld,
+                                        int(features.shape[1]), _dptr(features), _dptr(I), _dptr(Lam),
+                                        _dptr(D), _dptr(self.cva0),
+                                        _dptr(self.grad if with_grad else None), _dptr(self.ws), self.wsb,
+                                        _stream()))
+        return self.cva0, self.grad
 
     def __call__(self, market=None, path_begin: int = 0, with_grad: bool = True):
         km = market_struct(self.w.market if market is None else market)

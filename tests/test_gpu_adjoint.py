@@ -72,3 +72,27 @@ def test_autograd_function(lib):
     v.backward()
     _, grad = adj()
     assert np.allclose(p.grad.numpy(), npy(grad))
+
+
+@pytest.mark.parametrize("name", ["small_multi", "cva_at_scale"])
+def test_adjoint_from_forward_outputs_equals_own_forward(lib, name):
+    """cva_adjoint_forward on the first M paths of a 2M-path simulation (features with the extra
+    columns of the 29-input mode) gives cva_adjoint's results bit for bit."""
+    import torch
+    w = wl.small_multi(M=512) if name == "small_multi" else wl.cva_at_scale(M=1 << 12)
+    adj = lib.Adjoint(w)
+    cva0, grad = adj()
+    c_ref, g_ref = cva0.clone(), grad.clone()
+    s = lib.Solver(w.with_(M=2 * w.M), precision=lib.HSIM_FP32)
+    n1, C = w.grid.n_dates + 1, w.market.n_cpty
+    feats = torch.empty((n1, s.d, 2 * w.M), dtype=torch.float32, device="cuda")
+    I = torch.empty((n1, 2 * w.M), dtype=torch.float64, device="cuda")
+    Lam = torch.empty((n1, C, 2 * w.M), dtype=torch.float64, device="cuda")
+    D = torch.empty((n1, C, 2 * w.M), dtype=torch.float32, device="cuda")
+    lib.check(lib.lib().hsim_outer_paths(lib.ctypes.byref(s.km.struct), lib.ctypes.byref(s.kp.struct),
+                                         lib.ctypes.byref(s.g), w.seed, 0, 2 * w.M, lib.HSIM_FP32, s.fm,
+                                         lib._dptr(feats), lib._dptr(I), lib._dptr(Lam), lib._dptr(D),
+                                         None, lib._stream()))
+    cva0, grad = adj.from_forward(feats, I, Lam, D)
+    print(f"  {name}: CVA_0 {cva0.item():.10g} vs {c_ref.item():.10g}", flush=True)
+    assert torch.equal(cva0, c_ref) and torch.equal(grad, g_ref)
