@@ -46,10 +46,14 @@ def pilot(w, M: int, pred=None):
     return R, Q
 
 
-def cost_ratio(w, M: int, n_b=(1, 64), reps: int = 3) -> float:
-    """P from the times of (M, N) and (M, N') (l:ratio)."""
+def cost_ratio(w, M: int, n_b=(1, 1024), reps: int = 5) -> float:
+    """P from the times of (M, N) and (M, N') (l:ratio).  N' must be large enough for the inner
+    draws to change the time measurably (the outer path can cost thousands of draws)."""
     N, Np = n_b
     t, tp = _timed_solve(w, N, M, reps), _timed_solve(w, Np, M, reps)
+    if not tp > t * 1.05:
+        raise RuntimeError(f"timings {t:.3g} s (n_b={N}) and {tp:.3g} s (n_b={Np}) do not resolve the "
+                           "cost ratio: use a larger M or n_b'")
     return (tp * N - t * Np) / (t - tp)
 
 

@@ -28,7 +28,7 @@ def test_pilot_moments_match_oracle(lib):
 def test_chooser_split_is_consistent(lib):
     from paper_2211_17005_amd import oversim
     w = wl.plain_fp64()
-    out = oversim.choose(w, Psi=1e8, M_pilot=1 << 15)
+    out = oversim.choose(w, Psi=1e8, M_pilot=1 << 16)
     R, Q = out["R"], out["Q"]
     print(f"  P {out['P']:.1f}  N {out['N']:.2f}  M {out['M']:.0f}  "
           f"N*_i range {out['N_dates'].min():.2f}..{out['N_dates'].max():.2f}", flush=True)
