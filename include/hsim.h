@@ -186,6 +186,16 @@ int hsim_targets_cva(const hsim_grid* grid, int32_t n_cpty, int64_t M, int32_t n
                      void* target_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,
                      void* stream);
 
+/* Intensity-based targets (Section 4.2, the intensity route eq:CVAint): the conditional
+ * expectation of the inner average above given the outer path,
+ *   T~_i = exp(I_i) sum_{j=i+1}^{n} sum_c D^c_j (exp(-Lambda^c_{j-1}) - exp(-Lambda^c_j)),
+ * the minimal-variance regression target (no inner draws).  Lambda_dev [n+1][C][M] as written
+ * by hsim_outer_paths; the rest as hsim_targets_cva (uniform weights, no n_b). */
+int hsim_targets_intensity(const hsim_grid* grid, int32_t n_cpty, int64_t M, int precision,
+                           const double* I_dev, const double* Lambda_dev, const void* D_dev,
+                           void* target_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,
+                           void* stream);
+
 /* The three stages above in one call: features_dev [n+1][d][M] (may be NULL),
  * target_dev [n+1][M], cva0_dev (one double).  The intermediate I, Lambda, D and counts
  * live in the workspace: hsim_workspace_bytes(HSIM_OP_FUSED, ...). */

@@ -341,6 +341,7 @@ int run_targets(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b, cons
   a.I = I;
   a.D = (const Real*)D;
   a.counts = counts;
+  a.Lam = nullptr;
   a.T = (Real*)T;
   a.partial = (double*)ws;
   a.cva0 = cva0;
@@ -470,6 +471,37 @@ int hsim_targets_cva(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b,
                                   target_dev, cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream)
              : run_targets<double>(g, n_cpty, M, n_b, n_b_per_block, block_paths, I_dev, D_dev, counts_dev,
                                    target_dev, cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream);
+}
+
+int hsim_targets_intensity(const hsim_grid* g, int32_t n_cpty, int64_t M, int precision, const double* I_dev,
+                           const double* Lambda_dev, const void* D_dev, void* target_dev, double* cva0_dev,
+                           void* workspace_dev, size_t ws_bytes, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if ((rc = check_precision(precision))) return rc;
+  if ((rc = check_paths(0, M))) return rc;
+  if (n_cpty < 1 || n_cpty > HSIM_MAX_CPTY) return fail(HSIM_ERANGE, "n_cpty out of range");
+  if (!I_dev || !Lambda_dev || !D_dev || !target_dev || !cva0_dev) return fail(HSIM_EINVAL, "NULL array");
+  const size_t need = hsim_workspace_bytes(HSIM_OP_TARGETS, nullptr, g, M, 0);
+  if (ws_bytes < need || !workspace_dev) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, need);
+  auto run = [&](auto tag) -> int {
+    using Real = decltype(tag);
+    TargetArgs<Real> a;
+    memset(&a, 0, sizeof(a));
+    a.M = M;
+    a.n_dates = g->n_dates;
+    a.n_cpty = n_cpty;
+    a.n_b = 1;
+    a.I = I_dev;
+    a.D = (const Real*)D_dev;
+    a.Lam = Lambda_dev;
+    a.T = (Real*)target_dev;
+    a.partial = (double*)workspace_dev;
+    a.cva0 = cva0_dev;
+    const hipError_t e = launch_targets<Real>(a, (hipStream_t)stream);
+    return e == hipSuccess ? HSIM_OK : device_error(e, "targets kernel launch");
+  };
+  return precision == HSIM_FP32 ? run(0.0f) : run(0.0);
 }
 
 static size_t partial_bytes_of(int64_t M) {

@@ -305,6 +305,10 @@ __global__ __launch_bounds__(1024) void inner_order_kernel(const int32_t* nb_blo
 // ------------------------------------------------------------------------------------
 // targets and CVA_0
 // ------------------------------------------------------------------------------------
+// T_i = exp(I_i) sum_{j > i} sum_c D^c_j w^c_j with w^c_j = counts^c_j / n_b (the inner average of
+// the pathwise loss) or, in the intensity form, w^c_j = exp(-Lambda^c_{j-1}) - exp(-Lambda^c_j)
+// (its conditional expectation given the outer path: one default per counterparty falls in
+// (t_{j-1}, t_j] with that probability).
 template <typename Real>
 __global__ __launch_bounds__(kTargetBlock) void targets_kernel(const TargetArgs<Real> a) {
   __shared__ double red[kTargetBlock];
@@ -315,13 +319,19 @@ __global__ __launch_bounds__(kTargetBlock) void targets_kernel(const TargetArgs<
   double t0 = 0.0;
   if (kl < M) {
     const int nb = a.nb_block ? a.nb_block[kl / a.block_paths] : a.n_b;
-    const double inv_nb = 1.0 / (double)nb;
-    double S = 0.0;                        // sum_{j > i} sum_c D^c_j counts^c_j
+    const double inv_nb = a.Lam ? 1.0 : 1.0 / (double)nb;
+    double S = 0.0;                        // sum_{j > i} sum_c D^c_j w^c_j
     a.T[(int64_t)n * M + kl] = (Real)0;
     for (int i = n - 1; i >= 0; --i) {
       for (int c = 0; c < C; ++c) {
         const int64_t o = ((int64_t)(i + 1) * C + c) * M + kl;
-        S += (double)a.D[o] * (double)a.counts[o];
+        double wgt;
+        if (a.Lam) {
+          wgt = exp(-a.Lam[((int64_t)i * C + c) * M + kl]) - exp(-a.Lam[o]);
+        } else {
+          wgt = (double)a.counts[o];
+        }
+        S += (double)a.D[o] * wgt;
       }
       const double Ti = S * exp(a.I[(int64_t)i * M + kl]) * inv_nb;
       a.T[(int64_t)i * M + kl] = (Real)Ti;

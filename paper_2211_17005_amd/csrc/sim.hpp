@@ -73,7 +73,8 @@ struct TargetArgs {
   int32_t block_paths;
   const double* I;
   const Real* D;
-  const int32_t* counts;
+  const int32_t* counts;             // default counts of the inner draws, or
+  const double* Lam;                 // (intensity form, counts null) the intensity integrals [n+1][C][M]
   Real* T;                           // [n+1][M]
   double* partial;                   // [ceil(M / kTargetBlock)]
   double* cva0;                      // one double

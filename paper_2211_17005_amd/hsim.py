@@ -85,6 +85,8 @@ def lib():
                                                sz, vp]),
         "hsim_targets_cva": (ctypes.c_int, [G_, i32, i64, i32, vp, i32, ctypes.c_int, vp, vp, vp,
                                             vp, vp, vp, sz, vp]),
+        "hsim_targets_intensity": (ctypes.c_int, [G_, i32, i64, ctypes.c_int, vp, vp, vp, vp, vp,
+                                                  vp, sz, vp]),
         "hsim_inner_defaults_cva": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i32, vp, i32,
                                                    ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, sz,
                                                    vp]),
@@ -307,6 +309,23 @@ def targets_cva(grid, n_cpty: int, I, D, counts, n_b: int = 1, n_b_per_block=Non
                                  _dptr(I), _dptr(D), _dptr(counts), _dptr(T), _dptr(cva0),
                                  _dptr(ws), wsb, _stream()))
     torch.cuda.current_stream().synchronize() if nbt is not None else None
+    return T, cva0
+
+
+def targets_intensity(grid, n_cpty: int, I, Lam, D, precision: int = HSIM_FP32):
+    """hsim_targets_intensity: the conditional-expectation targets (no inner draws) and CVA_0."""
+    import torch
+    M = I.shape[-1]
+    _expect(I, torch.float64, (grid.n_dates + 1, M), "I")
+    _expect(Lam, torch.float64, (grid.n_dates + 1, n_cpty, M), "Lam")
+    _expect(D, _real(precision), (grid.n_dates + 1, n_cpty, M), "D")
+    T = torch.empty((grid.n_dates + 1, M), dtype=_real(precision), device="cuda")
+    cva0 = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = grid_struct(grid)
+    wsb = lib().hsim_workspace_bytes(OP_TARGETS, None, ctypes.byref(g), M, precision)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    check(lib().hsim_targets_intensity(ctypes.byref(g), n_cpty, M, precision, _dptr(I), _dptr(Lam),
+                                       _dptr(D), _dptr(T), _dptr(cva0), _dptr(ws), wsb, _stream()))
     return T, cva0
 
 

@@ -148,3 +148,15 @@ def test_inner_rejects_bad_nb(hs, cpu_only):
                                         None, 0, None) == -3
     assert hs.lib().hsim_inner_defaults(ctypes.byref(g), 1, 0, 0, 64, 0, dummy, 64, dummy, dummy,
                                         dummy, need - 1, None) == -3
+
+
+def test_intensity_targets_reject_bad_arguments(hs, cpu_only):
+    g = hs.grid_struct(wl.Grid(10.0, 50, 25))
+    dummy = ctypes.c_void_p(256)
+    need = hs.lib().hsim_workspace_bytes(hs.OP_TARGETS, None, ctypes.byref(g), 64, hs.HSIM_FP32)
+    f = hs.lib().hsim_targets_intensity
+    assert f(ctypes.byref(g), 0, 64, 1, dummy, dummy, dummy, dummy, dummy, dummy, need, None) == -2
+    assert f(ctypes.byref(g), 1, 0, 1, dummy, dummy, dummy, dummy, dummy, dummy, need, None) == -1
+    assert f(ctypes.byref(g), 1, 64, 1, dummy, None, dummy, dummy, dummy, dummy, need, None) == -1
+    assert f(ctypes.byref(g), 1, 64, 1, dummy, dummy, dummy, dummy, dummy, dummy, need - 1,
+             None) == -3
