@@ -24,5 +24,9 @@ Parity status of the functions (what pins each one, besides the GPU path):
   oversim (chooser)      R, Q recovered on a hierarchical sample of known variances; the
                          variance law's minimiser over a brute-force grid equals N*; the
                          proof's rearranged variance equals the direct one; l:ratio exact
+  branch (nested / twin) prefix equals the outer path bitwise; CIR closed form of the
+                         conditional survival increments; twin estimator unbiased on
+                         samples of known conditional mean (e:val1 for B = 2); tower
+                         property against independent outer paths
 """
-from . import philox, closed_forms, model, inner, pipeline, regression, sensitivities, oversim  # noqa: F401
+from . import philox, closed_forms, model, inner, pipeline, regression, sensitivities, oversim, branch  # noqa: F401

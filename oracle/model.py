@@ -50,8 +50,15 @@ def dates_per_reset(w) -> int:
     return int(round(q))
 
 
-def simulate_outer(w, paths, market=None) -> OuterPaths:
-    """Euler scheme of Appendix B on the fine grid; values stored at the pricing dates."""
+def simulate_outer(w, paths, market=None, branch=None, branch_date: int = 0) -> OuterPaths:
+    """Euler scheme of Appendix B on the fine grid; values stored at the pricing dates.
+
+    With ``branch`` (one continuation index per entry of ``paths``), the sub-steps of
+    dates after ``branch_date`` draw the branch normals of that continuation: up to
+    t_{branch_date} the path is the outer path itself, afterwards a conditionally
+    independent copy of its future (the re-simulation of Section 3.3's twin Monte
+    Carlo and of the nested Monte Carlo benchmark of Section 4.3).
+    """
     m = w.market if market is None else market
     n_e, C, d_w, n_z = dims(w)
     n, n_sub = w.grid.n_dates, w.grid.n_sub
@@ -79,7 +86,10 @@ def simulate_outer(w, paths, market=None) -> OuterPaths:
     for i in range(n):
         for j in range(n_sub):
             s = i * n_sub + j
-            z = philox.outer_normals(w.seed, paths, s, n_z)
+            if branch is not None and i >= branch_date:
+                z = philox.outer_normals(w.seed, paths, s, n_z, branch=branch)
+            else:
+                z = philox.outer_normals(w.seed, paths, s, n_z)
             Wc = z[:, :d_w] @ L.T                        # correlated market increments
             r_old, g_old = r.copy(), np.maximum(g, 0.0)
             # domestic Vasicek under Q^0

@@ -9,6 +9,8 @@ Counter layout (global indices only, never launch geometry):
   outer normals:  (k, s, f >> 2, 0)  path k, global sub-step s, normal index f
   inner defaults: (k, l >> 2, c, 1)  draw l, counterparty c
   network init:   (layer, idx >> 2, date, 2)
+  branch normals: (k, s, 16 b + (f >> 2), 3)  continuation b of path k after its branching
+                  date (at most 64 normals per sub-step, so f >> 2 < 16)
 Key = (seed mod 2^32, seed >> 32).  The word used is ``l & 3`` (``f & 3``).  Keeping
 the draw index l in the first counter word makes the first n_b' draws of every
 (path, counterparty) a prefix of the first n_b draws, for any n_b >= n_b'.
@@ -30,6 +32,7 @@ ROUNDS = 10
 TAG_OUTER = 0
 TAG_INNER = 1
 TAG_INIT = 2
+TAG_BRANCH = 3
 
 
 def key_from_seed(seed: int):
@@ -75,17 +78,24 @@ def words(seed, c0, c1, c2, c3):
     return philox4x32_10(c0, c1, c2, c3, k0, k1)
 
 
-def outer_normals(seed: int, paths: np.ndarray, s: int, n_z: int) -> np.ndarray:
+def outer_normals(seed: int, paths: np.ndarray, s: int, n_z: int, branch=None) -> np.ndarray:
     """Normals z[path, f], f < n_z, for global sub-step s.
 
     Call (k, s, g, 0) gives words (w0..w3); normals 4g, 4g+1 come from (w0, w1)
-    and 4g+2, 4g+3 from (w2, w3), cosine branch first.
+    and 4g+2, 4g+3 from (w2, w3), cosine branch first.  With ``branch`` (one index
+    b >= 0 per path) the call is (k, s, 16 b + g, 3): the normals of continuation b.
     """
     paths = np.asarray(paths, dtype=np.uint64)
     n_calls = (n_z + 3) // 4
+    if n_calls > 16:
+        raise ValueError("at most 64 normals per sub-step")
     out = np.empty((paths.shape[0], 4 * n_calls))
     for g in range(n_calls):
-        w0, w1, w2, w3 = words(seed, paths, s, g, TAG_OUTER)
+        if branch is None:
+            w0, w1, w2, w3 = words(seed, paths, s, g, TAG_OUTER)
+        else:
+            c2 = 16 * np.asarray(branch, dtype=np.uint64) + np.uint64(g)
+            w0, w1, w2, w3 = words(seed, paths, s, c2, TAG_BRANCH)
         z0, z1 = box_muller(uniform(w0), uniform(w1))
         z2, z3 = box_muller(uniform(w2), uniform(w3))
         out[:, 4 * g + 0] = z0
