@@ -70,6 +70,7 @@ enum hsim_features { HSIM_FEAT_FACTORS = 0, HSIM_FEAT_FACTORS_PLUS = 1 };
 /* Limits of this build. */
 #define HSIM_MAX_CCY 16
 #define HSIM_MAX_CPTY 16
+#define HSIM_MAX_BRANCH (1 << 24)
 #define HSIM_MAX_DATES 512
 #define HSIM_MAX_PERIODS 64
 
@@ -217,7 +218,36 @@ int hsim_inner_defaults_cva(const hsim_market* market, const hsim_portfolio* boo
 int hsim_oversim_moments(const hsim_grid* grid, int64_t M, int precision, const void* T1_dev,
                          const void* T2_dev, const void* pred_dev, double* moments_dev, void* stream);
 
-enum hsim_op { HSIM_OP_INNER = 1, HSIM_OP_TARGETS = 2, HSIM_OP_FUSED = 3, HSIM_OP_ADJOINT = 4 };
+/* Branched re-simulation (Section 3.3 twin Monte Carlo validation, e:val1/e:val2; the
+ * nested Monte Carlo benchmark of Section 4.3 on eq:CVAint).  For every outer path k of
+ * [path_begin, path_begin + M) and continuation b < n_branch (1 <= n_branch <= HSIM_MAX_BRANCH,
+ * M * n_branch <= 2^31), the path is simulated exactly as hsim_outer_paths simulates it up to
+ * the pricing date t_date (same Philox words and arithmetic), then with the branch words
+ * (k, s, 16 b + (f >> 2), 3) after it, and
+ *   xi_dev[b][k] = sum_{j > date} sum_c LGD_c exp(I_date - I_j) (MtM^c_j)^+
+ *                  (exp(-Lambda^c_{j-1}) - exp(-Lambda^c_j))          (double, [n_branch][M]),
+ * accumulated in FP64.  Given the state at t_date the samples of one path are independent
+ * with conditional mean the CVA of eq:CVAint; 0 <= date <= n (date = n gives 0).  Market,
+ * book and precision as hsim_outer_paths.  No workspace. */
+int hsim_branch_cva(const hsim_market* market, const hsim_portfolio* book, const hsim_grid* grid,
+                    uint64_t seed, int64_t path_begin, int64_t M, int32_t date, int32_t n_branch,
+                    int precision, double* xi_dev, void* stream);
+
+/* Nested and twin Monte Carlo errors of a prediction phi_dev [M] (float if FP32 else double;
+ * NULL: phi = 0) against the continuation samples xi_dev [n_branch][M] of hsim_branch_cva,
+ * n_branch >= 2.  With nu = mean_b xi and U = sum_{b != b'} xi_b xi_b' / (B (B-1)),
+ * out_dev[6] (double, device) receives the path means, reduced in FP64 in a fixed order, of
+ *   [0] nu  [1] nu^2  [2] U (unbiased for CVA^2)  [3] (phi - nu)^2 (nested error, biased by
+ *   Var/B)  [4] phi^2 - 2 phi nu + U (twin error, unbiased for E[(phi - CVA)^2]; for B = 2
+ *   exactly e:val1)  [5] phi.
+ * The paper's relative error is sqrt(out[4] / out[2]).  Needs
+ * hsim_workspace_bytes(HSIM_OP_BRANCH, NULL, NULL, M, precision) bytes of workspace. */
+int hsim_branch_errors(int64_t M, int32_t n_branch, int precision, const void* phi_dev,
+                       const double* xi_dev, double* out_dev, void* workspace_dev, size_t ws_bytes,
+                       void* stream);
+
+enum hsim_op { HSIM_OP_INNER = 1, HSIM_OP_TARGETS = 2, HSIM_OP_FUSED = 3, HSIM_OP_ADJOINT = 4,
+               HSIM_OP_BRANCH = 5 };
 
 /* Device workspace (bytes) an operation needs for M paths and the given market/grid. */
 size_t hsim_workspace_bytes(int op, const hsim_market* market, const hsim_grid* grid,

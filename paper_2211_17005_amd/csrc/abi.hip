@@ -504,12 +504,56 @@ int hsim_targets_intensity(const hsim_grid* g, int32_t n_cpty, int64_t M, int pr
   return precision == HSIM_FP32 ? run(0.0f) : run(0.0);
 }
 
+int hsim_branch_cva(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed,
+                    int64_t path_begin, int64_t M, int32_t date, int32_t n_branch, int precision, double* xi_dev,
+                    void* stream) {
+  int rc = check_precision(precision);
+  if (rc) return rc;
+  if (!xi_dev) return fail(HSIM_EINVAL, "xi_dev is NULL");
+  if ((rc = check_grid(g))) return rc;
+  if (date < 0 || date > g->n_dates) return fail(HSIM_EINVAL, "branching date %d outside [0, %d]", date, g->n_dates);
+  if (n_branch < 1 || n_branch > HSIM_MAX_BRANCH) return fail(HSIM_ERANGE, "n_branch %d outside [1, %d]", n_branch, HSIM_MAX_BRANCH);
+  if (M > 0 && M * (int64_t)n_branch > ((int64_t)1 << 31))
+    return fail(HSIM_ERANGE, "M * n_branch = %lld exceeds 2^31", (long long)(M * (int64_t)n_branch));
+  auto run = [&](auto tag) -> int {
+    using Real = decltype(tag);
+    SimArgs<Real> a;
+    const int r = build_sim_args<Real>(m, p, g, seed, path_begin, M, HSIM_FEAT_FACTORS, a);
+    if (r) return r;
+    BranchArgs b;
+    b.date = date;
+    b.n_branch = n_branch;
+    b.xi = xi_dev;
+    const hipError_t e = launch_branch<Real>(a, b, (hipStream_t)stream);
+    return e == hipSuccess ? HSIM_OK : device_error(e, "branch kernel launch");
+  };
+  return precision == HSIM_FP32 ? run(0.0f) : run(0.0);
+}
+
+int hsim_branch_errors(int64_t M, int32_t n_branch, int precision, const void* phi_dev, const double* xi_dev,
+                       double* out_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+  int rc = check_precision(precision);
+  if (rc) return rc;
+  if ((rc = check_paths(0, M))) return rc;
+  if (n_branch < 2 || n_branch > HSIM_MAX_BRANCH)
+    return fail(HSIM_ERANGE, "n_branch %d outside [2, %d] (the twin estimator needs two continuations)", n_branch,
+                HSIM_MAX_BRANCH);
+  if (!xi_dev || !out_dev) return fail(HSIM_EINVAL, "NULL array");
+  const size_t need = align256(branch_stats_bytes(M));
+  if (ws_bytes < need || !workspace_dev) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, need);
+  const hipError_t e = launch_branch_stats(M, n_branch, precision == HSIM_FP32, phi_dev, xi_dev,
+                                           (double*)workspace_dev, out_dev, (hipStream_t)stream);
+  return e == hipSuccess ? HSIM_OK : device_error(e, "branch statistics launch");
+}
+
 static size_t partial_bytes_of(int64_t M) {
   return align256(sizeof(double) * (size_t)((M + kTargetBlock - 1) / kTargetBlock));
 }
 
 size_t hsim_workspace_bytes(int op, const hsim_market* m, const hsim_grid* g, int64_t M, int precision) {
-  if (!g || M < 1) return 0;
+  if (M < 1) return 0;
+  if (op == HSIM_OP_BRANCH) return align256(branch_stats_bytes(M));
+  if (!g) return 0;
   const size_t n1 = (size_t)g->n_dates + 1;
   const size_t partial = partial_bytes_of(M);
   switch (op) {

@@ -24,7 +24,7 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
-enum : uint32_t { kTagOuter = 0, kTagInner = 1, kTagInit = 2 };
+enum : uint32_t { kTagOuter = 0, kTagInner = 1, kTagInit = 2, kTagBranch = 3 };
 
 __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
@@ -70,10 +70,12 @@ __device__ __forceinline__ void box_muller(double ua, double ub, double& z0, dou
 }
 
 // Four normals from one Philox call: (w0, w1) -> z0, z1 and (w2, w3) -> z2, z3.
+// Counter (k, s, c2, tag): c2 = g for the outer path, 16 b + g for its continuation b
+// (tag kTagBranch) after a branching date.
 template <typename Real>
-__device__ __forceinline__ void normals4(uint32_t k, uint32_t s, uint32_t g, uint32_t key0,
-                                         uint32_t key1, Real z[4]) {
-  const u32x4 w = philox4x32_10(k, s, g, kTagOuter, key0, key1);
+__device__ __forceinline__ void normals4(uint32_t k, uint32_t s, uint32_t c2, uint32_t key0,
+                                         uint32_t key1, Real z[4], uint32_t tag = kTagOuter) {
+  const u32x4 w = philox4x32_10(k, s, c2, tag, key0, key1);
   box_muller(uniform_of<Real>(w.x), uniform_of<Real>(w.y), z[0], z[1]);
   box_muller(uniform_of<Real>(w.z), uniform_of<Real>(w.w), z[2], z[3]);
 }

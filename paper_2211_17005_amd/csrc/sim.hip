@@ -9,7 +9,11 @@
 //                   the n_b inner draws per counterparty are resolved to a default date by
 //                   the rule of e:tau (Lambda_j >= -log u), counted per date.
 //   targets_kernel  one lane per path: the suffix sums of eq:CVA_portfolio over the date
-//                   histogram give T_i; FP64 block partials give CVA_0 in a fixed order.
+//                   histogram give T_i (or, in the intensity form of eq:CVAint, over the
+//                   survival increments); FP64 block partials give CVA_0 in a fixed order.
+//   branch_kernel   one lane per (continuation, path): the outer path up to a branching
+//                   date, then an independent continuation whose eq:CVAint sample is
+//                   accumulated in registers (nested / twin Monte Carlo).
 //
 // The outer state is kept in registers for the whole horizon; the only HBM traffic is
 // the per-date outputs.  All parameters that are the same for every lane (Cholesky
@@ -38,14 +42,29 @@ struct OuterState {
   double Lam[NC];
 };
 
-// Price the book and emit every per-date output at date i.
+// 1 / ZC^e_t(t + delta) from r^e at a reset date: the next floating coupon's discount.
 template <typename Real, int NE, int NC>
-__device__ __forceinline__ void price_and_emit(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st,
-                                               int i, int64_t kl) {
+__device__ __forceinline__ Real reset_inv_zc(const SimArgs<Real>& a, int e, Real re) {
+  const Real* lnA = a.lnA + e * (a.n_dates + 1);
+  const Real* Bv = a.Bv + e * (a.n_dates + 1);
+  return exp_r(-lnA[a.q] + Bv[a.q] * re);
+}
+
+// The reset bookkeeping of pricing date i without the pricing itself.
+template <typename Real, int NE, int NC>
+__device__ __forceinline__ void reset_only(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st, int i) {
+  if ((i % a.q) != 0) return;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) st.invzc[e] = reset_inv_zc<Real, NE, NC>(a, e, st.r[e]);
+}
+
+// Value of the book per counterparty at pricing date i (updates the reset state).
+template <typename Real, int NE, int NC>
+__device__ __forceinline__ void price(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st, int i,
+                                      Real mtm[NC]) {
   const int n = a.n_dates;
   const int q = a.q;
   const int P2 = a.n_periods + 2;
-  const int64_t M = a.M;
   const bool reset = (i % q) == 0;
   const bool coupon = reset && i > 0;
   const int kfirst = i / q + 1;             // first reset date strictly after t_i
@@ -54,7 +73,6 @@ __device__ __forceinline__ void price_and_emit(const SimArgs<Real>& a, OuterStat
   const int pmin = min((i + q - 1) / q, a.n_periods + 1);
   const int pnow = min(i / q, a.n_periods + 1);
 
-  Real mtm[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) mtm[c] = (Real)0;
 
@@ -89,9 +107,17 @@ __device__ __forceinline__ void price_and_emit(const SimArgs<Real>& a, OuterStat
       if (coupon) v -= a.CW2[base + pmin] + a.W1[base + pnow];
       mtm[c] += fx * v;
     }
-    if (reset) st.invzc[e] = exp_r(-lnA[q] + Bv[q] * re);
+    if (reset) st.invzc[e] = reset_inv_zc<Real, NE, NC>(a, e, re);
   }
+}
 
+// Price the book and emit every per-date output at date i.
+template <typename Real, int NE, int NC>
+__device__ __forceinline__ void price_and_emit(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st,
+                                               int i, int64_t kl) {
+  const int64_t M = a.M;
+  Real mtm[NC];
+  price<Real, NE, NC>(a, st, i, mtm);
   const double beta = exp(-st.I);
   a.I[(int64_t)i * M + kl] = st.I;
 #pragma unroll
@@ -122,16 +148,7 @@ __device__ __forceinline__ void price_and_emit(const SimArgs<Real>& a, OuterStat
 }
 
 template <typename Real, int NE, int NC>
-__global__ __launch_bounds__(kOuterBlock) __attribute__((amdgpu_waves_per_eu(NE > 4 ? 2 : 4)))
-void outer_kernel(const SimArgs<Real> a) {
-  constexpr int DW = 2 * NE - 1;
-  constexpr int NZ = DW + NC;
-  constexpr int NCALL = (NZ + 3) / 4;
-  const int64_t kl = (int64_t)blockIdx.x * kOuterBlock + threadIdx.x;
-  if (kl >= a.M) return;
-  const uint32_t k = a.path_begin + (uint32_t)kl;
-
-  OuterState<Real, NE, NC> st;
+__device__ __forceinline__ void init_state(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st) {
 #pragma unroll
   for (int e = 0; e < NE; ++e) st.r[e] = a.r0[e];
 #pragma unroll
@@ -143,61 +160,164 @@ void outer_kernel(const SimArgs<Real> a) {
     st.Lam[c] = 0.0;
   }
   st.I = 0.0;
-  price_and_emit<Real, NE, NC>(a, st, 0, kl);
+}
 
-  for (int i = 0; i < a.n_dates; ++i) {
-    for (int j = 0; j < a.n_sub; ++j) {
-      // Keep the uniform parameters (kernel arguments, Cholesky factor) in memory: they are
-      // re-read through the scalar cache every sub-step instead of being hoisted into
-      // registers, which would cost more registers than the whole path state.
-      asm volatile("" ::: "memory");
-      using CL = CoefLayout<NE, NC>;
-      const Real* cf = a.coef;
-      const Real dt = a.dt;
-      const double hdt = a.half_dt;
-      const uint32_t s = (uint32_t)(i * a.n_sub + j);
-      // Normals arrive four at a time; each market normal z_f is folded at once into the
-      // correlated increments W_p += L_{pf} z_f (p >= f), each CIR normal drives its
-      // intensity step, so only W and the current four normals are live.
-      Real W[DW];
+// The n_sub Euler sub-steps from t_i to t_{i+1}, normals from the Philox counters
+// (k, s, c2 + (f >> 2), tag).
+template <typename Real, int NE, int NC>
+__device__ __forceinline__ void advance(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st, int i,
+                                        uint32_t k, uint32_t c2, uint32_t tag) {
+  constexpr int DW = 2 * NE - 1;
+  constexpr int NZ = DW + NC;
+  constexpr int NCALL = (NZ + 3) / 4;
+  for (int j = 0; j < a.n_sub; ++j) {
+    // Keep the uniform parameters (kernel arguments, Cholesky factor) in memory: they are
+    // re-read through the scalar cache every sub-step instead of being hoisted into
+    // registers, which would cost more registers than the whole path state.
+    asm volatile("" ::: "memory");
+    using CL = CoefLayout<NE, NC>;
+    const Real* cf = a.coef;
+    const Real dt = a.dt;
+    const double hdt = a.half_dt;
+    const uint32_t s = (uint32_t)(i * a.n_sub + j);
+    // Normals arrive four at a time; each market normal z_f is folded at once into the
+    // correlated increments W_p += L_{pf} z_f (p >= f), each CIR normal drives its
+    // intensity step, so only W and the current four normals are live.
+    Real W[DW];
 #pragma unroll
-      for (int p = 0; p < DW; ++p) W[p] = (Real)0;
+    for (int p = 0; p < DW; ++p) W[p] = (Real)0;
 #pragma unroll
-      for (int g = 0; g < NCALL; ++g) {
-        Real z[4];
-        normals4<Real>(k, s, (uint32_t)g, a.key0, a.key1, z);
+    for (int g = 0; g < NCALL; ++g) {
+      Real z[4];
+      normals4<Real>(k, s, c2 + (uint32_t)g, a.key0, a.key1, z, tag);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int f = 4 * g + t;
-          if (f < DW) {
+      for (int t = 0; t < 4; ++t) {
+        const int f = 4 * g + t;
+        if (f < DW) {
 #pragma unroll
-            for (int p = f; p < DW; ++p) W[p] += a.chol[p * (p + 1) / 2 + f] * z[t];
-          } else if (f < NZ) {
-            const int c = f - DW;
-            const Real gp = st.g[c] > (Real)0 ? st.g[c] : (Real)0;
-            // compensated (Fast2Sum) state update: the CIR diffusion amplifies rounding
-            // errors of the state near zero, so the increment's rounding error is carried
-            const Real inc = cf[CL::g_add + c] - cf[CL::g_kd + c] * gp + cf[CL::g_vol + c] * sqrt_r(gp) * z[t]
-                             + st.gcomp[c];
-            const Real gs = st.g[c] + inc;
-            st.gcomp[c] = inc - (gs - st.g[c]);
-            st.g[c] = gs;
-            const Real gn = st.g[c] > (Real)0 ? st.g[c] : (Real)0;
-            st.Lam[c] += hdt * ((double)gp + (double)gn);
-          }
+          for (int p = f; p < DW; ++p) W[p] += a.chol[p * (p + 1) / 2 + f] * z[t];
+        } else if (f < NZ) {
+          const int c = f - DW;
+          const Real gp = st.g[c] > (Real)0 ? st.g[c] : (Real)0;
+          // compensated (Fast2Sum) state update: the CIR diffusion amplifies rounding
+          // errors of the state near zero, so the increment's rounding error is carried
+          const Real inc = cf[CL::g_add + c] - cf[CL::g_kd + c] * gp + cf[CL::g_vol + c] * sqrt_r(gp) * z[t]
+                           + st.gcomp[c];
+          const Real gs = st.g[c] + inc;
+          st.gcomp[c] = inc - (gs - st.g[c]);
+          st.g[c] = gs;
+          const Real gn = st.g[c] > (Real)0 ? st.g[c] : (Real)0;
+          st.Lam[c] += hdt * ((double)gp + (double)gn);
         }
       }
-      const Real r0old = st.r[0];
-#pragma unroll
-      for (int e = 1; e < NE; ++e)
-        st.x[e - 1] += (r0old - st.r[e]) * dt + cf[CL::x_add + e - 1] + cf[CL::x_vol + e - 1] * W[NE + e - 1];
-#pragma unroll
-      for (int e = 0; e < NE; ++e)
-        st.r[e] = st.r[e] + cf[CL::r_adt + e] * (cf[CL::r_lvl + e] - st.r[e]) + cf[CL::r_vol + e] * W[e];
-      st.I += hdt * ((double)r0old + (double)st.r[0]);
     }
+    const Real r0old = st.r[0];
+#pragma unroll
+    for (int e = 1; e < NE; ++e)
+      st.x[e - 1] += (r0old - st.r[e]) * dt + cf[CL::x_add + e - 1] + cf[CL::x_vol + e - 1] * W[NE + e - 1];
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+      st.r[e] = st.r[e] + cf[CL::r_adt + e] * (cf[CL::r_lvl + e] - st.r[e]) + cf[CL::r_vol + e] * W[e];
+    st.I += hdt * ((double)r0old + (double)st.r[0]);
+  }
+}
+
+template <typename Real, int NE, int NC>
+__global__ __launch_bounds__(kOuterBlock) __attribute__((amdgpu_waves_per_eu(NE > 4 ? 2 : 4)))
+void outer_kernel(const SimArgs<Real> a) {
+  const int64_t kl = (int64_t)blockIdx.x * kOuterBlock + threadIdx.x;
+  if (kl >= a.M) return;
+  const uint32_t k = a.path_begin + (uint32_t)kl;
+  OuterState<Real, NE, NC> st;
+  init_state<Real, NE, NC>(a, st);
+  price_and_emit<Real, NE, NC>(a, st, 0, kl);
+  for (int i = 0; i < a.n_dates; ++i) {
+    advance<Real, NE, NC>(a, st, i, k, 0u, kTagOuter);
     price_and_emit<Real, NE, NC>(a, st, i + 1, kl);
   }
+}
+
+// ------------------------------------------------------------------------------------
+// branched re-simulation (nested and twin Monte Carlo)
+// ------------------------------------------------------------------------------------
+// Lane (b, k): outer path k exactly as outer_kernel simulates it up to t_date (pricing
+// replaced by the reset bookkeeping it would do), then continuation b with the branch
+// counters; the intensity-form sample of eq. CVAint at t_date is accumulated on the way:
+//   xi = sum_{j > date} sum_c LGD_c exp(I_date - I_j) (MtM^c_j)^+
+//        (exp(-Lambda^c_{j-1}) - exp(-Lambda^c_j)).
+template <typename Real, int NE, int NC>
+__global__ __launch_bounds__(kOuterBlock) __attribute__((amdgpu_waves_per_eu(NE > 4 ? 2 : 4)))
+void branch_kernel(const SimArgs<Real> a, const BranchArgs b) {
+  const int64_t lane = (int64_t)blockIdx.x * kOuterBlock + threadIdx.x;
+  if (lane >= a.M * b.n_branch) return;
+  const int64_t kl = lane % a.M;
+  const uint32_t br = (uint32_t)(lane / a.M);
+  const uint32_t k = a.path_begin + (uint32_t)kl;
+  OuterState<Real, NE, NC> st;
+  init_state<Real, NE, NC>(a, st);
+  reset_only<Real, NE, NC>(a, st, 0);
+  for (int i = 0; i < b.date; ++i) {
+    advance<Real, NE, NC>(a, st, i, k, 0u, kTagOuter);
+    reset_only<Real, NE, NC>(a, st, i + 1);
+  }
+  const double I0 = st.I;
+  double surv[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) surv[c] = exp(-st.Lam[c]);
+  double xi = 0.0;
+  for (int i = b.date; i < a.n_dates; ++i) {
+    advance<Real, NE, NC>(a, st, i, k, 16u * br, kTagBranch);
+    Real mtm[NC];
+    price<Real, NE, NC>(a, st, i + 1, mtm);
+    const double disc = exp(I0 - st.I);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double sn = exp(-st.Lam[c]);
+      const double pos = mtm[c] > (Real)0 ? (double)mtm[c] : 0.0;
+      xi += (double)a.lgd[c] * disc * pos * (surv[c] - sn);
+      surv[c] = sn;
+    }
+  }
+  b.xi[lane] = xi;
+}
+
+// Per-path nested / twin statistics over the continuations, FP64 block partials
+// (row r of `partial` holds statistic r of every block):
+//   nu, nu^2, U = ((sum xi)^2 - sum xi^2) / (B (B-1)), (phi - nu)^2, phi^2 - 2 phi nu + U, phi.
+template <typename PhiT>
+__global__ __launch_bounds__(kTargetBlock) void branch_stats_kernel(int64_t M, int32_t B, const PhiT* phi,
+                                                                   const double* xi, double* partial,
+                                                                   int64_t nblk) {
+  __shared__ double red[kBranchStats][kTargetBlock];
+  const int64_t k = (int64_t)blockIdx.x * kTargetBlock + threadIdx.x;
+  double v[kBranchStats] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (k < M) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < B; ++b) {
+      const double x = xi[(int64_t)b * M + k];
+      s1 += x;
+      s2 += x * x;
+    }
+    const double nu = s1 / B;
+    const double U = (s1 * s1 - s2) / ((double)B * (double)(B - 1));
+    const double f = phi ? (double)phi[k] : 0.0;
+    v[0] = nu;
+    v[1] = nu * nu;
+    v[2] = U;
+    v[3] = (f - nu) * (f - nu);
+    v[4] = f * f - 2.0 * f * nu + U;
+    v[5] = f;
+  }
+#pragma unroll
+  for (int r = 0; r < kBranchStats; ++r) red[r][threadIdx.x] = v[r];
+  __syncthreads();
+  for (int w = kTargetBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int r = 0; r < kBranchStats; ++r) red[r][threadIdx.x] += red[r][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < kBranchStats) partial[threadIdx.x * nblk + blockIdx.x] = red[threadIdx.x][0];
 }
 
 // ------------------------------------------------------------------------------------
@@ -436,6 +556,41 @@ hipError_t launch_inner(const InnerArgs& a, hipStream_t stream) {
 }
 
 template <typename Real>
+hipError_t launch_branch(const SimArgs<Real>& a, const BranchArgs& b, hipStream_t stream) {
+  const dim3 grid((unsigned)((a.M * b.n_branch + kOuterBlock - 1) / kOuterBlock));
+#define X(ne, nc)                                                                                  \
+  if (a.n_ccy == ne && a.n_cpty == nc) {                                                           \
+    hipLaunchKernelGGL((branch_kernel<Real, ne, nc>), grid, dim3(kOuterBlock), 0, stream, a, b);    \
+    return hipGetLastError();                                                                      \
+  }
+  HSIM_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+size_t branch_stats_bytes(int64_t M) {
+  return (size_t)kBranchStats * (size_t)((M + kTargetBlock - 1) / kTargetBlock) * sizeof(double);
+}
+
+hipError_t launch_branch_stats(int64_t M, int32_t B, bool phi_fp32, const void* phi, const double* xi,
+                               double* partial, double* out, hipStream_t stream) {
+  const int64_t nblk = (M + kTargetBlock - 1) / kTargetBlock;
+  if (phi_fp32)
+    hipLaunchKernelGGL((branch_stats_kernel<float>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, M, B,
+                       (const float*)phi, xi, partial, nblk);
+  else
+    hipLaunchKernelGGL((branch_stats_kernel<double>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, M, B,
+                       (const double*)phi, xi, partial, nblk);
+  hipError_t e = hipGetLastError();
+  for (int r = 0; r < kBranchStats && e == hipSuccess; ++r) {
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kTargetBlock), 0, stream, partial + r * nblk, nblk,
+                       1.0 / (double)M, out + r);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+template <typename Real>
 hipError_t launch_targets(const TargetArgs<Real>& a, hipStream_t stream) {
   const int64_t nblk = (a.M + kTargetBlock - 1) / kTargetBlock;
   hipLaunchKernelGGL((targets_kernel<Real>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, a);
@@ -465,6 +620,8 @@ hipError_t launch_normals_fill(uint64_t seed, int64_t path_begin, int64_t count,
 
 template hipError_t launch_outer<float>(const SimArgs<float>&, hipStream_t);
 template hipError_t launch_outer<double>(const SimArgs<double>&, hipStream_t);
+template hipError_t launch_branch<float>(const SimArgs<float>&, const BranchArgs&, hipStream_t);
+template hipError_t launch_branch<double>(const SimArgs<double>&, const BranchArgs&, hipStream_t);
 template hipError_t launch_targets<float>(const TargetArgs<float>&, hipStream_t);
 template hipError_t launch_targets<double>(const TargetArgs<double>&, hipStream_t);
 template hipError_t launch_normals_fill<float>(uint64_t, int64_t, int64_t, int32_t, int32_t, float*,

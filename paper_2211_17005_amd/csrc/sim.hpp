@@ -80,6 +80,14 @@ struct TargetArgs {
   double* cva0;                      // one double
 };
 
+// Branched re-simulation: continuations b < n_branch of every path after pricing date `date`.
+struct BranchArgs {
+  int32_t date;
+  int32_t n_branch;
+  double* xi;                        // [n_branch][M] intensity-form samples at t_date
+};
+constexpr int kBranchStats = 6;      // nu, nu^2, U, (phi - nu)^2, phi^2 - 2 phi nu + U, phi
+
 // offsets into SimArgs::coef
 template <int NE, int NC>
 struct CoefLayout {
@@ -104,6 +112,13 @@ hipError_t launch_inner(const InnerArgs& a, hipStream_t stream);
 size_t inner_order_bytes(int64_t M);
 template <typename Real>
 hipError_t launch_targets(const TargetArgs<Real>& a, hipStream_t stream);
+template <typename Real>
+hipError_t launch_branch(const SimArgs<Real>& a, const BranchArgs& b, hipStream_t stream);
+// Workspace of launch_branch_stats (FP64 block partials of the kBranchStats statistics).
+size_t branch_stats_bytes(int64_t M);
+// out[kBranchStats] = path means of the statistics; phi may be null (phi = 0).
+hipError_t launch_branch_stats(int64_t M, int32_t B, bool phi_fp32, const void* phi, const double* xi,
+                               double* partial, double* out, hipStream_t stream);
 hipError_t launch_philox_fill(uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
                               int64_t k_begin, int64_t count, uint32_t* out, hipStream_t s);
 template <typename Real>

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libhsim.so")
 
 HSIM_FP64, HSIM_FP32 = 0, 1
 FEAT_FACTORS, FEAT_FACTORS_PLUS = 0, 1
-OP_INNER, OP_TARGETS, OP_FUSED, OP_ADJOINT = 1, 2, 3, 4
+OP_INNER, OP_TARGETS, OP_FUSED, OP_ADJOINT, OP_BRANCH = 1, 2, 3, 4, 5
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_f64p = ctypes.POINTER(ctypes.c_double)
@@ -100,6 +100,8 @@ def lib():
         "cva_regress_predict": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32,
                                                vp, vp, vp, vp]),
         "hsim_oversim_moments": (ctypes.c_int, [G_, i64, ctypes.c_int, vp, vp, vp, vp, vp]),
+        "hsim_branch_cva": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i32, i32, ctypes.c_int, vp, vp]),
+        "hsim_branch_errors": (ctypes.c_int, [i64, i32, ctypes.c_int, vp, vp, vp, vp, sz, vp]),
         "cva_adjoint_forward": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i64, i32, vp, vp, vp, vp, vp,
                                                vp, vp, sz, vp]),
     }
@@ -327,6 +329,44 @@ def targets_intensity(grid, n_cpty: int, I, Lam, D, precision: int = HSIM_FP32):
     check(lib().hsim_targets_intensity(ctypes.byref(g), n_cpty, M, precision, _dptr(I), _dptr(Lam),
                                        _dptr(D), _dptr(T), _dptr(cva0), _dptr(ws), wsb, _stream()))
     return T, cva0
+
+
+BRANCH_STATS = ("cva_mean", "cva_sq_nested", "cva_sq", "mse_nested", "mse_twin", "phi_mean")
+
+
+def branch_cva(w, date: int, n_branch: int, precision: int = HSIM_FP32, path_begin: int = 0,
+               M: Optional[int] = None, fixed=None, market=None):
+    """hsim_branch_cva: xi [n_branch][M] (float64, device), the eq. CVAint samples of
+    n_branch continuations of every path after pricing date `date`."""
+    import torch
+    m = w.market if market is None else market
+    M = w.M if M is None else M
+    xi = torch.empty((n_branch, M), dtype=torch.float64, device="cuda")
+    fixed = fixed_rates(m, w.portfolio) if fixed is None else fixed
+    km, kp = market_struct(m), portfolio_struct(w.portfolio, fixed)
+    g = grid_struct(w.grid)
+    check(lib().hsim_branch_cva(ctypes.byref(km.struct), ctypes.byref(kp.struct), ctypes.byref(g),
+                                w.seed, path_begin, M, date, n_branch, precision, _dptr(xi),
+                                _stream()))
+    return xi
+
+
+def branch_errors(xi, phi=None) -> dict:
+    """hsim_branch_errors: nested / twin Monte Carlo statistics (names in BRANCH_STATS) of the
+    prediction phi [M] (float32 or float64 device tensor, or None for phi = 0)."""
+    import torch
+    B, M = xi.shape
+    _expect(xi, torch.float64, (B, M), "xi")
+    precision = HSIM_FP64
+    if phi is not None:
+        precision = HSIM_FP32 if phi.dtype == torch.float32 else HSIM_FP64
+        _expect(phi, _real(precision), (M,), "phi")
+    out = torch.empty(len(BRANCH_STATS), dtype=torch.float64, device="cuda")
+    wsb = lib().hsim_workspace_bytes(OP_BRANCH, None, None, M, precision)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    check(lib().hsim_branch_errors(M, B, precision, _dptr(phi), _dptr(xi), _dptr(out), _dptr(ws),
+                                   wsb, _stream()))
+    return dict(zip(BRANCH_STATS, out.cpu().tolist()))
 
 
 def oversim_moments(grid, T1, T2, pred=None, precision: int = HSIM_FP32):

@@ -160,3 +160,24 @@ def test_intensity_targets_reject_bad_arguments(hs, cpu_only):
     assert f(ctypes.byref(g), 1, 64, 1, dummy, None, dummy, dummy, dummy, dummy, need, None) == -1
     assert f(ctypes.byref(g), 1, 64, 1, dummy, dummy, dummy, dummy, dummy, dummy, need - 1,
              None) == -3
+
+
+def test_branch_entry_points_reject_bad_arguments(hs, cpu_only):
+    w = wl.small_multi()
+    km = hs.market_struct(w.market)
+    kp = hs.portfolio_struct(w.portfolio, np.zeros(w.portfolio.n_swaps))
+    g = hs.grid_struct(w.grid)
+    dummy = ctypes.c_void_p(256)
+    f = hs.lib().hsim_branch_cva
+    args = (ctypes.byref(km.struct), ctypes.byref(kp.struct), ctypes.byref(g), 0, 0)
+    assert f(*args, 64, -1, 2, 1, dummy, None) == -1                     # date < 0
+    assert f(*args, 64, w.grid.n_dates + 1, 2, 1, dummy, None) == -1     # date > n
+    assert f(*args, 64, 3, 0, 1, dummy, None) == -2                      # no continuation
+    assert f(*args, 1 << 20, 3, 1 << 12, 1, dummy, None) == -2           # M * B > 2^31
+    assert f(*args, 64, 3, 2, 1, None, None) == -1                       # no output
+    e = hs.lib().hsim_branch_errors
+    need = hs.lib().hsim_workspace_bytes(hs.OP_BRANCH, None, None, 1000, 1)
+    assert need >= 6 * 4 * 8
+    assert e(1000, 1, 1, None, dummy, dummy, dummy, need, None) == -2   # B < 2
+    assert e(1000, 2, 1, None, dummy, dummy, dummy, need - 1, None) == -3
+    assert e(0, 2, 1, None, dummy, dummy, dummy, need, None) == -1
