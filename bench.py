@@ -14,7 +14,9 @@ M * n_b * n_dates / (seconds per step).
 Also reported: per-stage times (HIP events on the launch stream), the roofline of the
 dominant kernel (and of the simulation kernel), the plain-FP32 comparison solve (same
 simulation, sequential per-date FP32 regression in plain PyTorch, sensitivities by central
-finite differences with common random numbers), and the FP64 oracle on the host cores.
+finite differences with common random numbers), the FP64 oracle on the host cores, and,
+outside the timed step, the twin and nested Monte Carlo errors of the fitted network at
+t = 5y on out-of-sample paths (branched re-simulation).
 
 Prints one JSON line.  The CPU baseline runs before the GPU is touched.
 """
@@ -251,6 +253,37 @@ def oversim_sweep(hsim, torch, M: int, reps: int = 3):
             "ms_per_call": ms, "path_steps_per_s": steps / (ms / 1e3), "dtype": "f32 (f64 integrals)"}
 
 
+# ------------------------------------------------------------------------------- validation
+def validation(hsim, torch, w, cfg, model, dates, date: int = 50, paths: int = 1 << 14,
+               b_nested: int = 128):
+    """The fitted network at one pricing date on out-of-sample outer paths [M, M + paths):
+    twin Monte Carlo L2 error (Section 3.3, two continuations per path) and the nested Monte
+    Carlo benchmark (Section 4.3: b_nested continuations, eq. CVAint inner estimator)."""
+    test = hsim.outer_paths(w, precision=hsim.HSIM_FP32, path_begin=w.M, M=paths)
+    j = dates.index(date)
+    phi = hsim.regress_predict(cfg, [date], test["features"], model[j:j + 1].contiguous())[0]
+    phi = phi.contiguous()
+    out = {"date": date, "t_years": date * w.grid.horizon / w.grid.n_dates, "paths": paths,
+           "out_of_sample": True}
+    for tag, B in (("twin", 2), ("nested", b_nested)):
+        hsim.branch_cva(w, date, B, path_begin=w.M, M=paths)          # untimed first call
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        xi = hsim.branch_cva(w, date, B, path_begin=w.M, M=paths)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = hsim.branch_errors(xi, phi)
+        out[tag] = {"branches": B, "ms": ms,
+                    "lane_steps_per_s": paths * B * w.grid.n_dates * w.grid.n_sub / (ms / 1e3),
+                    "rel_l2_twin": float(np.sqrt(max(st["mse_twin"], 0.0) / st["cva_sq"])),
+                    "rel_l2_vs_nested": float(np.sqrt(st["mse_nested"] / st["cva_sq_nested"])),
+                    "cva_mean": st["cva_mean"], "phi_mean": st["phi_mean"]}
+        del xi
+    return out
+
+
 # ------------------------------------------------------------------------------- GPU step
 def main():
     ap = argparse.ArgumentParser()
@@ -270,6 +303,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (scale of the FETCH/WRITE counters)")
     ap.add_argument("--plain-dates", type=int, default=2)
+    ap.add_argument("--no-validation", action="store_true",
+                    help="skip the twin / nested Monte Carlo check of the fitted network")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -441,6 +476,10 @@ def main():
     if not args.sim_only and not args.no_sweep:
         sweep = oversim_sweep(hsim, torch, args.sweep_M)
 
+    valid = None
+    if not args.sim_only and not args.no_validation:
+        valid = validation(hsim, torch, w, cfg, model, dates)
+
     rec_out = {
         "metric": "outer x inner path-steps/s of the whole CVA-with-sensitivities solve (1 GPU)",
         "value": value,
@@ -469,6 +508,7 @@ def main():
         "cva0": cva0.item(),
         "plain_fp32": plain,
         "oversim_sweep": sweep,
+        "validation": valid,
         "cpu_baseline": cpu,
         "wall_s": wall,
     }
