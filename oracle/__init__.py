@@ -28,5 +28,9 @@ Parity status of the functions (what pins each one, besides the GPU path):
                          conditional survival increments; twin estimator unbiased on
                          samples of known conditional mean (e:val1 for B = 2); tower
                          property against independent outer paths
+  alive-group targets    dead draws carry no loss; the alive group's sum of squares equals the
+  (one counterparty)     weighted row's for any prediction; weight x target = inner average;
+                         many draws approach the survival-conditioned conditional mean
+  weighted regression    integer weights equal duplicated rows (loss, gradient, refit)
 """
 from . import philox, closed_forms, model, inner, pipeline, regression, sensitivities, oversim, branch  # noqa: F401

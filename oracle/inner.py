@@ -56,6 +56,30 @@ def targets(xi: np.ndarray) -> np.ndarray:
     return xi.mean(axis=2)
 
 
+def alive_targets(xi: np.ndarray, jstar: np.ndarray):
+    """Grouped form of the per-inner-sample regression for one counterparty (Section 3.2).
+
+    The paper regresses xi^{k,l}_i on (X^{k,l}_i, Y^k_i) over all (path, draw) samples, with X the
+    default indicator 1{tau <= t_i}.  With one counterparty the samples of path k split into the
+    dead group (X = 1), whose xi_i is identically 0 (no default remains to be paid), and the alive
+    group (X = 0, A^k_i = #{l : j*_l > i} samples); over the alive group
+        sum_l (phi - xi^{k,l}_i)^2 = A^k_i (phi - mean_alive xi)^2 + const,
+    so the regression on the alive branch is the weighted regression of the alive mean on Y with
+    weight A^k_i / n_b: it learns the CVA at t_i given survival of the client.
+    Returns (target [n+1, P] = mean of xi over the alive draws, 0 where none is alive;
+    weight [n+1, P] = A / n_b).  xi [n+1, P, n_b], jstar [P, n_b, 1].
+    """
+    if jstar.shape[2] != 1:
+        raise ValueError("the alive-group form is exact for one counterparty only")
+    n = xi.shape[0] - 1
+    n_b = xi.shape[2]
+    alive = jstar[None, :, :, 0] > np.arange(n + 1)[:, None, None]      # [n+1, P, n_b]
+    A = alive.sum(axis=2)
+    s = np.where(alive, xi, 0.0).sum(axis=2)
+    target = np.where(A > 0, s / np.maximum(A, 1), 0.0)
+    return target, A / n_b
+
+
 def default_counts(jstar: np.ndarray, n: int) -> np.ndarray:
     """cnt[n+1, C, P]: number of inner draws of each path defaulting at date j."""
     P, _, C = jstar.shape

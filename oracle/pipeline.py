@@ -2,7 +2,9 @@
 
 Arrays are returned in the layouts the library uses, so tests compare them
 element by element:  features [n+1, d, P], I [n+1, P], Lam/MtM/D/cnt [n+1, C, P],
-T [n+1, P].  P is the number of paths of the requested range.
+T [n+1, P].  P is the number of paths of the requested range.  With ``with_alive`` (one
+counterparty) also T_alive / W_alive [n+1, P], the grouped per-inner-sample targets and weights
+of ``inner.alive_targets``.
 """
 from __future__ import annotations
 
@@ -13,12 +15,13 @@ from . import inner, model
 
 def simulate(w, path_begin: int = 0, count: int | None = None, n_b: int | None = None,
              chunk: int = 512, market=None, fixed=None, with_moments: bool = False,
-             n_b_per_path: np.ndarray | None = None):
+             n_b_per_path: np.ndarray | None = None, with_alive: bool = False):
     count = w.M - path_begin if count is None else count
     n_b = w.n_b if n_b is None else n_b
     m = w.market if market is None else market
     fixed = model.fixed_rates(w, m) if fixed is None else fixed
-    res = {k: [] for k in ("features", "I", "Lam", "MtM", "D", "cnt", "T", "mu", "var")}
+    res = {k: [] for k in ("features", "I", "Lam", "MtM", "D", "cnt", "T", "mu", "var",
+                           "T_alive", "W_alive")}
     for c0 in range(path_begin, path_begin + count, chunk):
         paths = np.arange(c0, min(c0 + chunk, path_begin + count))
         outer = model.simulate_outer(w, paths, m)
@@ -35,6 +38,10 @@ def simulate(w, path_begin: int = 0, count: int | None = None, n_b: int | None =
             xi = inner.pathwise_loss(outer.I, mt, m.lgd, js)
             res["cnt"].append(inner.default_counts(js, w.grid.n_dates))
             res["T"].append(inner.targets(xi))
+            if with_alive:
+                ta, wa = inner.alive_targets(xi, js)
+                res["T_alive"].append(ta)
+                res["W_alive"].append(wa)
         else:
             # uneven oversimulation: each path uses its own n_b (a prefix of the draws)
             T = np.empty((w.grid.n_dates + 1, paths.shape[0]))

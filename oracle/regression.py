@@ -22,6 +22,12 @@ Readings taken where the listing is garbled or silent:
   * inputs standardised per date (population mean/std, std 0 -> 1); targets
     divided by their root mean square (no shift, so positivity is kept); a date
     whose targets are all 0 is not trained and predicts 0.
+
+Row weights (optional, w >= 0): every loss becomes (1/|rows|) sum w (pred - y)^2 and the
+refit solves the weighted normal equations.  With the grouped form of the per-inner-sample
+regression (``inner.alive_targets``), the weighted loss over outer paths equals the paper's
+loss over all (path, draw) samples of the group up to a constant; integer weights equal
+duplicated rows.  The scaling statistics stay unweighted (they only fix units).
 """
 from __future__ import annotations
 
@@ -107,17 +113,19 @@ def predict_scaled(net: Net, X: np.ndarray, pos: int = 1) -> np.ndarray:
     return (np.maximum(f, 0.0) if pos else f) + net.mu
 
 
-def loss(net: Net, X, y, pos: int) -> float:
+def loss(net: Net, X, y, pos: int, w=None) -> float:
     r = predict_scaled(net, X, pos) - y
-    return float(np.mean(r * r))
+    return float(np.mean(r * r if w is None else w * r * r))
 
 
-def grads(net: Net, X, y, pos: int):
-    """Gradient of the batch loss (1/|batch|) sum (pred - y)^2 by backpropagation."""
+def grads(net: Net, X, y, pos: int, w=None):
+    """Gradient of the batch loss (1/|batch|) sum w (pred - y)^2 by backpropagation."""
     acts, pres, f = forward(net, X)
     B = X.shape[0]
     pred = (np.maximum(f, 0.0) if pos else f) + net.mu
     dpred = 2.0 * (pred - y) / B
+    if w is not None:
+        dpred = dpred * w
     df = dpred * (f > 0.0) if pos else dpred
     gW = [None] * len(net.W)
     gb = [None] * len(net.b)
@@ -168,7 +176,7 @@ class Adam:
 REFIT_RIDGE = 1e-4
 
 
-def refit_output_layer(net: Net, X, y) -> None:
+def refit_output_layer(net: Net, X, y, w=None) -> None:
     """Closed-form least squares for (W^{h+1}, b^{h+1}) with frozen hidden layers, mu fixed.
 
     Solved from the normal equations of [H, 1] with a ridge of REFIT_RIDGE times the mean
@@ -177,9 +185,10 @@ def refit_output_layer(net: Net, X, y) -> None:
     """
     acts, _, _ = forward(net, X)
     H = np.concatenate([acts[-1], np.ones((X.shape[0], 1))], axis=1)
-    G = H.T @ H
+    Hw = H if w is None else H * w[:, None]
+    G = Hw.T @ H
     lam = REFIT_RIDGE * np.trace(G) / G.shape[0]
-    sol = np.linalg.solve(G + lam * np.eye(G.shape[0]), H.T @ (y - net.mu))
+    sol = np.linalg.solve(G + lam * np.eye(G.shape[0]), Hw.T @ (y - net.mu))
     net.W[-1] = sol[:-1][None, :].copy()
     net.b[-1] = np.array([sol[-1]])
 
@@ -189,7 +198,7 @@ def batches(M: int, batch: int):
 
 
 def base_alg(net: Net, X, y, epochs: int, batch: int, lr=1e-3, beta1=0.9, beta2=0.999,
-             eps=1e-8) -> FitResult:
+             eps=1e-8, w=None) -> FitResult:
     """BaseAlg on standardised data; returns the best parameters found."""
     opt = Adam(net, lr, beta1, beta2, eps)
     pos = 0
@@ -198,12 +207,12 @@ def base_alg(net: Net, X, y, epochs: int, batch: int, lr=1e-3, beta1=0.9, beta2=
     hist = []
     for epoch in range(1, epochs + 1):
         for s, e in batches(X.shape[0], batch):
-            gW, gb, gmu = grads(net, X[s:e], y[s:e], pos)
+            gW, gb, gmu = grads(net, X[s:e], y[s:e], pos, None if w is None else w[s:e])
             opt.step(net, gW, gb, gmu)
         if epoch == epochs // 2:
-            refit_output_layer(net, X, y)
+            refit_output_layer(net, X, y, w)
             pos = 1
-        L = loss(net, X, y, 1)
+        L = loss(net, X, y, 1, w)
         hist.append(L)
         if L < best_loss:
             best_loss = L
@@ -219,14 +228,14 @@ def scaling(X: np.ndarray, y: np.ndarray) -> Scaling:
     return Scaling(mean, std, ys)
 
 
-def fit_date(X: np.ndarray, y: np.ndarray, cfg, init: Net, batch: int) -> FitResult:
-    """X [M, d] raw features, y [M] raw targets of one date."""
+def fit_date(X: np.ndarray, y: np.ndarray, cfg, init: Net, batch: int, w=None) -> FitResult:
+    """X [M, d] raw features, y [M] raw targets of one date, w [M] row weights or None."""
     sc = scaling(X, y)
     if sc.y_scale == 0.0:
         return FitResult(init.copy(), sc, 0.0, [], trained=False)
     Xs = (X - sc.x_mean) / sc.x_std
     ys = y / sc.y_scale
-    res = base_alg(init.copy(), Xs, ys, cfg.epochs, batch, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps)
+    res = base_alg(init.copy(), Xs, ys, cfg.epochs, batch, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, w)
     res.scaling = sc
     return res
 
@@ -244,7 +253,7 @@ def batch_size(cfg, M: int) -> int:
     return max(1, M // int(cfg.n_batches))
 
 
-def backward_learning(features: np.ndarray, T: np.ndarray, cfg, seed: int, dates=None):
+def backward_learning(features: np.ndarray, T: np.ndarray, cfg, seed: int, dates=None, W=None):
     """Algorithm 2: dates from the last to the first, each warm-started from the later one.
 
     features [n+1, d, M], T [n+1, M].  Returns {date: FitResult}.
@@ -256,16 +265,17 @@ def backward_learning(features: np.ndarray, T: np.ndarray, cfg, seed: int, dates
     net = init_net(d_in, cfg.hidden, cfg.width, seed)
     out = {}
     for i in dates:
-        res = fit_date(features[i].T, T[i], cfg, net, batch_size(cfg, M))
+        res = fit_date(features[i].T, T[i], cfg, net, batch_size(cfg, M), None if W is None else W[i])
         out[i] = res
         if res.trained:
             net = res.net.copy()
     return out
 
 
-def independent_fits(features: np.ndarray, T: np.ndarray, cfg, seed: int, dates):
+def independent_fits(features: np.ndarray, T: np.ndarray, cfg, seed: int, dates, W=None):
     """Batched reading: every date starts from the same initial network."""
     d_in = features.shape[1]
     M = T.shape[1]
     net = init_net(d_in, cfg.hidden, cfg.width, seed)
-    return {i: fit_date(features[i].T, T[i], cfg, net, batch_size(cfg, M)) for i in dates}
+    return {i: fit_date(features[i].T, T[i], cfg, net, batch_size(cfg, M), None if W is None else W[i])
+            for i in dates}
