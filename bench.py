@@ -397,7 +397,7 @@ def main():
         if args.sim_only:
             return
         hsim.check(L.cva_regress_fit(by(cfg), len(dates), dates_c.ctypes.data_as(hsim._c_i32p), n1, M, d,
-                                     P(feats), P(T), w.seed, P(model), None, P(mws_t), mws,
+                                     P(feats), P(T), None, w.seed, P(model), None, P(mws_t), mws,
                                      hsim._stream()))
         mark(4)
         # sensitivities on the first 2^16 of the paths just simulated (same market and seed): the

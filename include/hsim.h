@@ -187,6 +187,21 @@ int hsim_targets_cva(const hsim_grid* grid, int32_t n_cpty, int64_t M, int32_t n
                      void* target_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,
                      void* stream);
 
+/* Grouped per-inner-sample targets for one counterparty (Section 3.2 with X the default
+ * indicator; Algorithm 1's loss over all (path, draw) samples).  A draw whose client has
+ * defaulted by t_i has nothing left to lose, and over the A_i draws still alive at t_i the sum
+ * of squares equals A_i (phi - mean)^2 plus a constant, so the paper's regression on the alive
+ * branch is the weighted regression of
+ *   target_dev[i][k] = exp(I_i) / A_i * sum_{j=i+1}^{n} D_j counts_j     (0 when A_i = 0),
+ *   weight_dev[i][k] = A_i / n_b(k)  (float),   A_i = n_b(k) - sum_{j <= i} counts_j,
+ * on the market state (pass weight_dev as cva_regress_fit's W_dev): it learns the CVA given the
+ * client's survival to t_i.  D_dev and counts_dev are [n+1][1][M] (n_cpty = 1); CVA_0 and the
+ * other arguments as hsim_targets_cva (T_0 is the same, everyone is alive at t_0). */
+int hsim_targets_alive(const hsim_grid* grid, int64_t M, int32_t n_b, const int32_t* n_b_per_block,
+                       int32_t block_paths, int precision, const double* I_dev, const void* D_dev,
+                       const int32_t* counts_dev, void* target_dev, float* weight_dev,
+                       double* cva0_dev, void* workspace_dev, size_t ws_bytes, void* stream);
+
 /* Intensity-based targets (Section 4.2, the intensity route eq:CVAint): the conditional
  * expectation of the inner average above given the outer path,
  *   T~_i = exp(I_i) sum_{j=i+1}^{n} sum_c D^c_j (exp(-Lambda^c_{j-1}) - exp(-Lambda^c_j)),
@@ -296,13 +311,17 @@ size_t cva_regress_workspace_bytes(const cva_mlp_cfg* cfg, int32_t n_reg, int64_
 /* Fit one network per date j < n_reg on rows k < M of
  *   X_dev [n_dates_total][n_feat][M] (float, the features of hsim_outer_paths) and
  *   Y_dev [n_dates_total][M] (float, the targets of hsim_targets_cva),
+ *   W_dev [n_dates_total][M] (float row weights >= 0, or NULL for all 1: every loss becomes
+ *   (1/rows) sum_k w_k (pred_k - y_k)^2 and the refit solves the weighted normal equations;
+ *   with the weights of hsim_targets_alive this is the grouped form of the paper's
+ *   per-inner-sample regression, Section 3.2),
  * date index dates[j] (host array).  model_dev [n_reg][cva_regress_record_floats] receives
  * the best parameters and the input scaling; loss_hist_dev [n_reg][epochs] (may be NULL) the
  * full-sample loss after every epoch (in units of the scaled targets).  n_reg <= 512. */
 int cva_regress_fit(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,
-                    int64_t M, int32_t n_feat, const float* X_dev, const float* Y_dev, uint64_t seed,
-                    float* model_dev, float* loss_hist_dev, void* workspace_dev, size_t ws_bytes,
-                    void* stream);
+                    int64_t M, int32_t n_feat, const float* X_dev, const float* Y_dev,
+                    const float* W_dev, uint64_t seed, float* model_dev, float* loss_hist_dev,
+                    void* workspace_dev, size_t ws_bytes, void* stream);
 
 /* Predictions out_dev [n_reg][M] = ((f)^+ + mu) * y_scale of the fitted networks on X_dev. */
 int cva_regress_predict(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,

@@ -328,7 +328,7 @@ int run_outer(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g,
 template <typename Real>
 int run_targets(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b, const int32_t* nb_block,
                 int32_t block_paths, const double* I, const void* D, const int32_t* counts, void* T,
-                double* cva0, void* ws, size_t ws_bytes, hipStream_t stream) {
+                double* cva0, void* ws, size_t ws_bytes, hipStream_t stream, float* weight = nullptr) {
   const size_t need = hsim_workspace_bytes(HSIM_OP_TARGETS, nullptr, g, M, 0);
   if (ws_bytes < need || !ws) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, need);
   TargetArgs<Real> a;
@@ -343,6 +343,7 @@ int run_targets(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b, cons
   a.counts = counts;
   a.Lam = nullptr;
   a.T = (Real*)T;
+  a.weight = weight;
   a.partial = (double*)ws;
   a.cva0 = cva0;
   hipError_t e = launch_targets<Real>(a, stream);
@@ -471,6 +472,24 @@ int hsim_targets_cva(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b,
                                   target_dev, cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream)
              : run_targets<double>(g, n_cpty, M, n_b, n_b_per_block, block_paths, I_dev, D_dev, counts_dev,
                                    target_dev, cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream);
+}
+
+int hsim_targets_alive(const hsim_grid* g, int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
+                       int precision, const double* I_dev, const void* D_dev, const int32_t* counts_dev,
+                       void* target_dev, float* weight_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,
+                       void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if ((rc = check_precision(precision))) return rc;
+  if ((rc = check_paths(0, M))) return rc;
+  if ((rc = check_nb(n_b, n_b_per_block, block_paths))) return rc;
+  if (!I_dev || !D_dev || !counts_dev || !target_dev || !weight_dev || !cva0_dev)
+    return fail(HSIM_EINVAL, "NULL array");
+  return precision == HSIM_FP32
+             ? run_targets<float>(g, 1, M, n_b, n_b_per_block, block_paths, I_dev, D_dev, counts_dev, target_dev,
+                                  cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream, weight_dev)
+             : run_targets<double>(g, 1, M, n_b, n_b_per_block, block_paths, I_dev, D_dev, counts_dev, target_dev,
+                                   cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream, weight_dev);
 }
 
 int hsim_targets_intensity(const hsim_grid* g, int32_t n_cpty, int64_t M, int precision, const double* I_dev,

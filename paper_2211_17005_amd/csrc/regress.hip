@@ -182,7 +182,7 @@ struct Smem {
   static constexpr int SW = U + 16;
   static constexpr int w_bytes = (U * SW0 + (H - 1) * U * SW) * (int)sizeof(__bf16);
   static constexpr int a_bytes = (R * SW0 + H * R * SW) * (int)sizeof(__bf16);
-  static constexpr int f_count = 2 * H * U + 2 * U + 4 * R + 2 * D + 8;
+  static constexpr int f_count = 2 * H * U + 2 * U + 5 * R + 2 * D + 8;
   static constexpr int red_bytes = kMlpThreads * 16;
   static constexpr int bytes = w_bytes + a_bytes + f_count * 4 + red_bytes;
   static_assert(bytes <= 160 * 1024, "LDS of one workgroup");
@@ -205,9 +205,12 @@ struct Smem {
   __device__ float* ybuf() const { return fbuf() + R; }
   __device__ float* dpred() const { return ybuf() + R; }
   __device__ float* dff() const { return dpred() + R; }
-  __device__ float* xmean() const { return dff() + R; }
+  __device__ float* wbuf() const { return dff() + R; }     // row weights of the chunk (refit)
+  __device__ float* xmean() const { return wbuf() + R; }
   __device__ float* xinv() const { return xmean() + D; }
   __device__ float* scal() const { return xinv() + D; }   // [0] bout [1] mu [2] gbout [3] gmu [4] yscale
+  // [6..7] base of the row weights (null: none), kept in LDS so that no register holds it
+  __device__ const float** wbase() const { return (const float**)(scal() + 6); }
   __device__ char* red() const { return (char*)base + w_bytes + a_bytes + f_count * 4; }
   __device__ float* fpart() const { return (float*)red(); }   // [U/16/BO][R] output partials
   static constexpr int ldk(int l) { return l == 1 ? D : U; }
@@ -272,18 +275,25 @@ struct ChunkRegs {
   float y;                      // target of row t (threads t < 64)
 };
 
+// Target and weight of the row a thread t < 64 holds after staging a chunk.
+struct RowTarget {
+  float y, w;
+};
+
 // Per-thread source of the chunk staging for one date, set up once: thread t loads features
 // f0 .. f0 + 3 (f0 = 4 (t / 64)) of row t % 64 and, for t < 64, the target of row t.
 struct Feeder {
   const float* x;
-  const float* y;
+  const float* Y;               // uniform base of the targets
+  int64_t yo;                   // this thread's row offset in Y and in the weights (t < 64), else -1
   int64_t M;
   int nf, r;
   __device__ __forceinline__ Feeder(const MlpArgs& a, int date) {
     const int t = opaque_tid(), f0 = 4 * (t / kMlpRows);
     r = t % kMlpRows;
     x = a.X + ((int64_t)date * a.n_feat + f0) * a.M + r;
-    y = (a.Y != nullptr && t < kMlpRows) ? a.Y + (int64_t)date * a.M + t : nullptr;
+    Y = a.Y;
+    yo = (a.Y != nullptr && t < kMlpRows) ? (int64_t)date * a.M + t : -1;
     M = a.M;
     nf = max(0, min(4, a.d_in - f0));
   }
@@ -293,15 +303,22 @@ struct Feeder {
     const bool row_ok = r < n;
 #pragma unroll
     for (int q = 0; q < 4; ++q) c.x[q] = (row_ok && q < nf) ? x[q * M + r0] : 0.0f;
-    c.y = (y != nullptr && row_ok) ? y[r0] : 0.0f;
+    c.y = (yo >= 0 && row_ok) ? Y[yo + r0] : 0.0f;
     return c;
+  }
+  // weight of row r0 + t (1 without weights), from the base in LDS; read when the chunk is
+  // staged, not one chunk ahead, so the weights cost no register over the chunk
+  __device__ __forceinline__ float weight(const float* const* wbase, int64_t r0, int n) const {
+    const float* W = *wbase;
+    return (W != nullptr && yo >= 0 && r < n) ? W[yo + r0] : 1.0f;
   }
 };
 
-// Standardised inputs (BF16) into A(0); returns the scaled target of row t held by thread t < 64
-// (and stores it in ybuf for the refit).
+// Standardised inputs (BF16) into A(0); returns the scaled target and the weight of row t held by
+// thread t < 64 (and stores them in ybuf / wbuf, which hold them until the next chunk is staged).
 template <int U, int H>
-__device__ __forceinline__ float store_chunk(const Smem<U, H>& S, const ChunkRegs& c, int n, __bf16* dst = nullptr) {
+__device__ __forceinline__ RowTarget store_chunk(const Smem<U, H>& S, const ChunkRegs& c, float cw, int n,
+                                                 __bf16* dst = nullptr) {
   const int t = opaque_tid(), r = t % kMlpRows, f0 = 4 * (t / kMlpRows);
   const f32x4 mean = *(const f32x4*)&S.xmean()[f0];
   const f32x4 inv = *(const f32x4*)&S.xinv()[f0];
@@ -309,12 +326,14 @@ __device__ __forceinline__ float store_chunk(const Smem<U, H>& S, const ChunkReg
 #pragma unroll
   for (int q = 0; q < 4; ++q) v[q] = (__bf16)(r < n ? (c.x[q] - mean[q]) * inv[q] : 0.0f);
   *(bf16x4*)&(dst ? dst : S.A(0))[lidx(r, f0, S.SW0)] = v;
-  float y = 0.0f;
+  float y = 0.0f, w = 0.0f;
   if (t < kMlpRows) {
     y = t < n ? c.y / S.scal()[4] : 0.0f;
+    w = t < n ? cw : 0.0f;
     S.ybuf()[t] = y;
+    S.wbuf()[t] = w;
   }
-  return y;
+  return RowTarget{y, w};
 }
 
 // ------------------------------------------------------------------------------------------
@@ -791,24 +810,25 @@ __device__ float full_loss(const Smem<U, H>& S, const Lanes& ln, const Feeder& f
   const int64_t first = (int64_t)R * tm.member;
   auto rows = [&](int64_t r0) { return (int)max((int64_t)0, min((int64_t)R, a.M - r0)); };
   ChunkRegs c = feed.load(first, rows(first));
-  float y = store_chunk<U, H>(S, c, rows(first), scan_buf(S, 0));
+  RowTarget y = store_chunk<U, H>(S, c, feed.weight(S.wbase(), first, rows(first)), rows(first), scan_buf(S, 0));
   c = feed.load(first + stride, rows(first + stride));
   __syncthreads();
   int parity = 0;
   for (int64_t r0 = first; r0 < a.M; r0 += stride) {
     const int n = rows(r0);
-    float y_next = 0.0f;
+    RowTarget y_next{0.0f, 0.0f};
     forward_scan<U, H>(S, ln, scan_buf(S, parity));
     // the next chunk goes into the other buffer in this chunk's last-layer phase
     if (r0 + stride < a.M) {
-      y_next = store_chunk<U, H>(S, c, rows(r0 + stride), scan_buf(S, parity ^ 1));
+      y_next = store_chunk<U, H>(S, c, feed.weight(S.wbase(), r0 + stride, rows(r0 + stride)), rows(r0 + stride),
+                                 scan_buf(S, parity ^ 1));
       c = feed.load(r0 + 2 * stride, rows(r0 + 2 * stride));
     }
     __syncthreads();
     const int t = opaque_tid();
     if (t < n) {
-      const float d = fmaxf(output_of_row<U, H>(S, t), 0.0f) + S.scal()[1] - y;
-      e += (double)d * (double)d;
+      const float d = fmaxf(output_of_row<U, H>(S, t), 0.0f) + S.scal()[1] - y.y;
+      e += (double)y.w * (double)d * (double)d;
     }
     y = y_next;
     parity ^= 1;
@@ -848,13 +868,14 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
   for (int s = 0; s < GS; ++s)
 #pragma unroll
     for (int v = 0; v < 4; ++v) accG[s][v] = 0.0;
-  double hs = 0.0, hy = 0.0, ys = 0.0;        // thread u: sum h_u, sum h_u (y - mu); thread U: sum (y - mu)
+  // thread u: sum w h_u, sum w h_u (y - mu); thread U: sum w (y - mu), sum w
+  double hs = 0.0, hy = 0.0, ys = 0.0, sw = 0.0;
   const float mu = S.scal()[1];
   const int64_t stride = (int64_t)R * tm.G, first = (int64_t)R * tm.member;
   ChunkRegs c = feed.load(first, (int)max((int64_t)0, min((int64_t)R, a.M - first)));
   for (int64_t r0 = first; r0 < a.M; r0 += stride) {
     const int n = (int)min((int64_t)R, a.M - r0);
-    store_chunk<U, H>(S, c, n);
+    store_chunk<U, H>(S, c, feed.weight(S.wbase(), r0, n), n);
     if (r0 + stride < a.M) c = feed.load(r0 + stride, (int)min((int64_t)R, a.M - r0 - stride));
     __syncthreads();
     forward<U, H>(S, ln);
@@ -862,6 +883,15 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
     const LaneOffsets& oh = ln.o;
     if (n < R) {                              // rows beyond the sample take no part
       for (int e = tid; e < (R - n) * U; e += kMlpThreads) Hh[lidx(n + e / U, e % U, Smem<U, H>::SW)] = (__bf16)0.0f;
+      __syncthreads();
+    }
+    const bool weighted = *S.wbase() != nullptr;
+    if (weighted) {                           // weighted rows: H <- diag(sqrt w) H for the Gram tiles
+      for (int e = tid; e < n * U; e += kMlpThreads) {
+        const int r = e / U, u = e % U;
+        __bf16& h = Hh[lidx(r, u, Smem<U, H>::SW)];
+        h = (__bf16)((float)h * sqrtf(S.wbuf()[r]));
+      }
       __syncthreads();
     }
 #pragma unroll
@@ -879,12 +909,17 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
     if (tid < U) {
 #pragma unroll 1
       for (int r = 0; r < n; ++r) {
-        const double h = (float)Hh[lidx(r, tid, Smem<U, H>::SW)];
+        // with weights the stored row is sqrt(w) h: one more sqrt(w) gives w h
+        const double h = (double)(float)Hh[lidx(r, tid, Smem<U, H>::SW)] * (weighted ? sqrt((double)S.wbuf()[r]) : 1.0);
         hs += h;
         hy += h * (double)(S.ybuf()[r] - mu);
       }
     } else if (tid == U) {
-      for (int r = 0; r < n; ++r) ys += (double)(S.ybuf()[r] - mu);
+      for (int r = 0; r < n; ++r) {
+        const double w = S.wbuf()[r];
+        ys += w * (double)(S.ybuf()[r] - mu);
+        sw += w;
+      }
     }
     __syncthreads();
   }
@@ -903,7 +938,7 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
     G[U * N + tid] = hs;
     rhs[tid] = hy;
   } else if (tid == U) {
-    G[U * N + U] = (double)(tm.member == 0 ? a.M : 0);
+    G[U * N + U] = sw;
     rhs[U] = ys;
   }
   tm.sync();
@@ -999,7 +1034,10 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
     S.xmean()[e] = rec[L.xmean_off() + e];
     S.xinv()[e] = rec[L.xinv_off() + e];
   }
-  if (opaque_tid() == 0) S.scal()[4] = rec[L.yscale_off()];
+  if (opaque_tid() == 0) {
+    S.scal()[4] = rec[L.yscale_off()];
+    *S.wbase() = a.Wt;
+  }
   const bool trained = rec[L.trained_off()] != 0.0f;
   // initial parameters (written by the first workgroup of the team)
   for (int l = 1; l <= H + 1 && tm.member == 0; ++l) {
@@ -1072,7 +1110,7 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
       ChunkRegs c = feed.load(first, (int)max((int64_t)0, min((int64_t)R, b1 - first)));
       for (int64_t r0 = first; r0 < b1; r0 += cstride) {
         const int n = (int)min((int64_t)R, b1 - r0);
-        const float y = store_chunk<U, H>(S, c, n);
+        const float y = store_chunk<U, H>(S, c, feed.weight(S.wbase(), r0, n), n).y;
         if (r0 + cstride < b1) c = feed.load(r0 + cstride, (int)min((int64_t)R, b1 - r0 - cstride));
         __syncthreads();
         const Masks mk = forward<U, H>(S, ln);
@@ -1080,7 +1118,7 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
           const int r = opaque_tid();
           const float f = output_of_row<U, H>(S, r);
           const float pred = (pos ? fmaxf(f, 0.0f) : f) + S.scal()[1];
-          const float dp = r < n ? 2.0f * (pred - y) * inv_batch : 0.0f;
+          const float dp = r < n ? 2.0f * S.wbuf()[r] * (pred - y) * inv_batch : 0.0f;
           const float df = pos ? (f > 0.0f ? dp : 0.0f) : dp;
           S.dff()[r] = df;
           const float gm = wave_sum(dp), gb = wave_sum(df);
@@ -1165,7 +1203,7 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs 
   const Feeder feed(a, date);
   auto rows = [&](int64_t r0) { return (int)max((int64_t)0, min((int64_t)R, k1 - r0)); };
   ChunkRegs c = feed.load(k0, rows(k0));
-  store_chunk<U, H>(S, c, rows(k0), scan_buf(S, 0));
+  store_chunk<U, H>(S, c, 1.0f, rows(k0), scan_buf(S, 0));
   c = feed.load(k0 + R, rows(k0 + R));
   __syncthreads();
   int parity = 0;
@@ -1173,7 +1211,7 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs 
     const int n = rows(r0);
     forward_scan<U, H>(S, ln, scan_buf(S, parity));
     if (r0 + R < k1) {
-      store_chunk<U, H>(S, c, rows(r0 + R), scan_buf(S, parity ^ 1));
+      store_chunk<U, H>(S, c, 1.0f, rows(r0 + R), scan_buf(S, parity ^ 1));
       c = feed.load(r0 + 2 * R, rows(r0 + 2 * R));
     }
     __syncthreads();

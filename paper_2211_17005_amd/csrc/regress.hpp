@@ -45,6 +45,7 @@ struct MlpArgs {
   uint32_t key0, key1;
   const float* X;                 // [n+1][n_feat][M]
   const float* Y;                 // [n+1][M]
+  const float* Wt;                // [n+1][M] row weights, or null (all 1)
   float* model;                   // [n_reg][record]   (best parameters + scaling)
   float* cur;                     // [n_reg][n_params] current parameters (one copy per team)
   float* adam_m;                  // [n_reg][n_params]

@@ -113,8 +113,8 @@ size_t cva_regress_workspace_bytes(const cva_mlp_cfg* c, int32_t n_reg, int64_t 
 }
 
 int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int32_t n_dates_total, int64_t M,
-                    int32_t n_feat, const float* X_dev, const float* Y_dev, uint64_t seed, float* model_dev,
-                    float* loss_hist_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+                    int32_t n_feat, const float* X_dev, const float* Y_dev, const float* W_dev, uint64_t seed,
+                    float* model_dev, float* loss_hist_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
   MlpArgs a;
   int rc = fill_args(c, n_reg, dates, n_dates_total, M, n_feat, a);
   if (rc) return rc;
@@ -142,6 +142,7 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
   a.n_teams = n_teams;
   a.X = X_dev;
   a.Y = Y_dev;
+  a.Wt = W_dev;
   a.model = model_dev;
   a.loss_hist = loss_hist_dev;
   a.key0 = (uint32_t)seed;
@@ -185,6 +186,7 @@ int cva_regress_predict(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* date
   if (!X_dev || !model_dev || !out_dev) return fail(HSIM_EINVAL, "X, model and out must not be NULL");
   a.X = X_dev;
   a.Y = nullptr;
+  a.Wt = nullptr;
   a.model = (float*)model_dev;
   hipError_t e = launch_mlp_predict(a, out_dev, (hipStream_t)stream);
   return e == hipSuccess ? HSIM_OK : device_error(e, "prediction launch");

@@ -428,8 +428,12 @@ __global__ __launch_bounds__(1024) void inner_order_kernel(const int32_t* nb_blo
 // T_i = exp(I_i) sum_{j > i} sum_c D^c_j w^c_j with w^c_j = counts^c_j / n_b (the inner average of
 // the pathwise loss) or, in the intensity form, w^c_j = exp(-Lambda^c_{j-1}) - exp(-Lambda^c_j)
 // (its conditional expectation given the outer path: one default per counterparty falls in
-// (t_{j-1}, t_j] with that probability).
-template <typename Real>
+// (t_{j-1}, t_j] with that probability).  In the alive-group form (one counterparty) the sum is
+// divided by the A_i draws still alive at t_i instead of n_b, and A_i / n_b is the row weight:
+// A_i = n_b - (defaults up to t_i) = n_b - total + (defaults after t_i).
+enum TargetMode { kNested = 0, kIntensity = 1, kAlive = 2 };
+
+template <typename Real, int kMode>
 __global__ __launch_bounds__(kTargetBlock) void targets_kernel(const TargetArgs<Real> a) {
   __shared__ double red[kTargetBlock];
   const int64_t M = a.M;
@@ -439,21 +443,36 @@ __global__ __launch_bounds__(kTargetBlock) void targets_kernel(const TargetArgs<
   double t0 = 0.0;
   if (kl < M) {
     const int nb = a.nb_block ? a.nb_block[kl / a.block_paths] : a.n_b;
-    const double inv_nb = a.Lam ? 1.0 : 1.0 / (double)nb;
+    const double inv_nb = kMode == kIntensity ? 1.0 : 1.0 / (double)nb;
     double S = 0.0;                        // sum_{j > i} sum_c D^c_j w^c_j
+    int alive0 = 0, later = 0;             // alive form: draws alive at the horizon, defaults after t_i
+    if constexpr (kMode == kAlive) {
+      int total = 0;
+      for (int j = 1; j <= n; ++j) total += a.counts[(int64_t)j * M + kl];
+      alive0 = nb - total;
+      a.weight[(int64_t)n * M + kl] = (float)((double)alive0 * inv_nb);
+    }
     a.T[(int64_t)n * M + kl] = (Real)0;
     for (int i = n - 1; i >= 0; --i) {
       for (int c = 0; c < C; ++c) {
         const int64_t o = ((int64_t)(i + 1) * C + c) * M + kl;
         double wgt;
-        if (a.Lam) {
+        if constexpr (kMode == kIntensity) {
           wgt = exp(-a.Lam[((int64_t)i * C + c) * M + kl]) - exp(-a.Lam[o]);
         } else {
           wgt = (double)a.counts[o];
         }
         S += (double)a.D[o] * wgt;
       }
-      const double Ti = S * exp(a.I[(int64_t)i * M + kl]) * inv_nb;
+      double Ti;
+      if constexpr (kMode == kAlive) {
+        later += a.counts[(int64_t)(i + 1) * M + kl];
+        const int A = alive0 + later;
+        Ti = A > 0 ? S * exp(a.I[(int64_t)i * M + kl]) / (double)A : 0.0;
+        a.weight[(int64_t)i * M + kl] = (float)((double)A * inv_nb);
+      } else {
+        Ti = S * exp(a.I[(int64_t)i * M + kl]) * inv_nb;
+      }
       a.T[(int64_t)i * M + kl] = (Real)Ti;
       if (i == 0) t0 = Ti;
     }
@@ -593,7 +612,12 @@ hipError_t launch_branch_stats(int64_t M, int32_t B, bool phi_fp32, const void* 
 template <typename Real>
 hipError_t launch_targets(const TargetArgs<Real>& a, hipStream_t stream) {
   const int64_t nblk = (a.M + kTargetBlock - 1) / kTargetBlock;
-  hipLaunchKernelGGL((targets_kernel<Real>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, a);
+  if (a.Lam)
+    hipLaunchKernelGGL((targets_kernel<Real, kIntensity>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, a);
+  else if (a.weight)
+    hipLaunchKernelGGL((targets_kernel<Real, kAlive>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, a);
+  else
+    hipLaunchKernelGGL((targets_kernel<Real, kNested>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kTargetBlock), 0, stream, a.partial, nblk,

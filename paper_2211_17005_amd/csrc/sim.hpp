@@ -76,6 +76,7 @@ struct TargetArgs {
   const int32_t* counts;             // default counts of the inner draws, or
   const double* Lam;                 // (intensity form, counts null) the intensity integrals [n+1][C][M]
   Real* T;                           // [n+1][M]
+  float* weight;                     // alive-group form (one counterparty): [n+1][M] A_i / n_b, else null
   double* partial;                   // [ceil(M / kTargetBlock)]
   double* cva0;                      // one double
 };

@@ -96,7 +96,9 @@ def lib():
         "cva_regress_record_floats": (ctypes.c_int, [ctypes.POINTER(MlpCfg)]),
         "cva_regress_workspace_bytes": (sz, [ctypes.POINTER(MlpCfg), i32, i64]),
         "cva_regress_fit": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32, vp,
-                                           vp, u64, vp, vp, vp, sz, vp]),
+                                           vp, vp, u64, vp, vp, vp, sz, vp]),
+        "hsim_targets_alive": (ctypes.c_int, [G_, i64, i32, vp, i32, ctypes.c_int, vp, vp, vp, vp, vp,
+                                              vp, vp, sz, vp]),
         "cva_regress_predict": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32,
                                                vp, vp, vp, vp]),
         "hsim_oversim_moments": (ctypes.c_int, [G_, i64, ctypes.c_int, vp, vp, vp, vp, vp]),
@@ -314,6 +316,28 @@ def targets_cva(grid, n_cpty: int, I, D, counts, n_b: int = 1, n_b_per_block=Non
     return T, cva0
 
 
+def targets_alive(grid, I, D, counts, n_b: int = 1, n_b_per_block=None, block_paths: int = 64,
+                  precision: int = HSIM_FP32):
+    """hsim_targets_alive (one counterparty): the alive-group targets, their weights and CVA_0."""
+    import torch
+    M = I.shape[-1]
+    _expect(I, torch.float64, (grid.n_dates + 1, M), "I")
+    _expect(D, _real(precision), (grid.n_dates + 1, 1, M), "D")
+    _expect(counts, torch.int32, (grid.n_dates + 1, 1, M), "counts")
+    T = torch.empty((grid.n_dates + 1, M), dtype=_real(precision), device="cuda")
+    Wt = torch.empty((grid.n_dates + 1, M), dtype=torch.float32, device="cuda")
+    cva0 = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = grid_struct(grid)
+    wsb = lib().hsim_workspace_bytes(OP_TARGETS, None, ctypes.byref(g), M, precision)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    nb, nbt, bp = _nb_args(n_b, n_b_per_block, block_paths)
+    check(lib().hsim_targets_alive(ctypes.byref(g), M, nb, _dptr(nbt), bp, precision, _dptr(I),
+                                   _dptr(D), _dptr(counts), _dptr(T), _dptr(Wt), _dptr(cva0),
+                                   _dptr(ws), wsb, _stream()))
+    torch.cuda.current_stream().synchronize() if nbt is not None else None
+    return T, Wt, cva0
+
+
 def targets_intensity(grid, n_cpty: int, I, Lam, D, precision: int = HSIM_FP32):
     """hsim_targets_intensity: the conditional-expectation targets (no inner draws) and CVA_0."""
     import torch
@@ -451,12 +475,15 @@ def record_floats(cfg: MlpCfg) -> int:
     return n
 
 
-def regress_fit(cfg: MlpCfg, dates, X, Y, seed: int = 0, want_loss: bool = True):
-    """cva_regress_fit: X [n+1][n_feat][M] float32, Y [n+1][M] float32 (device)."""
+def regress_fit(cfg: MlpCfg, dates, X, Y, seed: int = 0, want_loss: bool = True, W=None):
+    """cva_regress_fit: X [n+1][n_feat][M] float32, Y [n+1][M] float32, W [n+1][M] float32 row
+    weights or None (device)."""
     import torch
     n1, n_feat, M = X.shape
     _expect(Y, torch.float32, (n1, M), "Y")
     _expect(X, torch.float32, (n1, n_feat, M), "X")
+    if W is not None:
+        _expect(W, torch.float32, (n1, M), "W")
     d = _i32(dates)
     n_reg = int(d.size)
     rec = record_floats(cfg)
@@ -465,7 +492,7 @@ def regress_fit(cfg: MlpCfg, dates, X, Y, seed: int = 0, want_loss: bool = True)
     wsb = lib().cva_regress_workspace_bytes(ctypes.byref(cfg), n_reg, M)
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     check(lib().cva_regress_fit(ctypes.byref(cfg), n_reg, d.ctypes.data_as(_c_i32p), n1, M, n_feat,
-                                _dptr(X), _dptr(Y), seed, _dptr(model), _dptr(loss), _dptr(ws), wsb,
+                                _dptr(X), _dptr(Y), _dptr(W), seed, _dptr(model), _dptr(loss), _dptr(ws), wsb,
                                 _stream()))
     return model, loss, ws
 
