@@ -32,5 +32,8 @@ Parity status of the functions (what pins each one, besides the GPU path):
   (one counterparty)     weighted row's for any prediction; weight x target = inner average;
                          many draws approach the survival-conditioned conditional mean
   weighted regression    integer weights equal duplicated rows (loss, gradient, refit)
+  per-sample rows        draw average = T; indicator increments = default counts; one
+                         counterparty: per-sample loss = grouped alive loss + const; labels =
+                         the loss definition as a double loop on a tiny case
 """
 from . import philox, closed_forms, model, inner, pipeline, regression, sensitivities, oversim, branch  # noqa: F401

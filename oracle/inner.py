@@ -80,6 +80,30 @@ def alive_targets(xi: np.ndarray, jstar: np.ndarray):
     return target, A / n_b
 
 
+def sample_rows(features: np.ndarray, xi: np.ndarray, jstar: np.ndarray):
+    """The paper's per-inner-sample regression data (Section 3.2, hierarchical simulation).
+
+    Every (outer path k, inner draw l) is one sample of I = {1..M} x {1..n_b}: its inputs at
+    date i are the market state Y^k_i (the path's features) followed by the default indicators
+    X^{k,l}_i = (1{tau_c <= t_i})_c, i.e. 1{j*_c <= i}; its label is the pathwise loss
+    xi^{k,l}_i.  Samples are stored in the order (l - 1) M + (k - 1), the order whose
+    contiguous slices are the paper's minibatches.
+    features [n+1, d, P], xi [n+1, P, n_b], jstar [P, n_b, C]  ->
+    X [n+1, d + C, n_b P], Y [n+1, n_b P].
+    """
+    n1, d, P = features.shape
+    n_b, C = jstar.shape[1], jstar.shape[2]
+    X = np.empty((n1, d + C, n_b * P))
+    Y = np.empty((n1, n_b * P))
+    for l in range(n_b):
+        cols = slice(l * P, (l + 1) * P)
+        X[:, :d, cols] = features
+        for i in range(n1):
+            X[i, d:, cols] = (jstar[:, l, :] <= i).T
+        Y[:, cols] = xi[:, :, l]
+    return X, Y
+
+
 def default_counts(jstar: np.ndarray, n: int) -> np.ndarray:
     """cnt[n+1, C, P]: number of inner draws of each path defaulting at date j."""
     P, _, C = jstar.shape
