@@ -187,6 +187,23 @@ int hsim_targets_cva(const hsim_grid* grid, int32_t n_cpty, int64_t M, int32_t n
                      void* target_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,
                      void* stream);
 
+/* The paper's per-inner-sample regression data (Section 3.2: Algorithm 2 on the hierarchical
+ * sample I = {paths} x {draws}, inputs (X_i, Y_i) with X the default indicators).  For every
+ * outer path k of [path_begin, path_begin + M) and inner draw l < n_b (the draws of
+ * hsim_inner_defaults: same Philox words, same default rule), sample r = l M + (k - path_begin)
+ * (the order whose contiguous slices are the paper's minibatches) gets at every date i
+ *   X_dev[i][f][r] = features_dev[i][f][k]             f < d  (market state Y^k_i)
+ *   X_dev[i][d + c][r] = 1{j*_c <= i}                  c < C  (default indicators X^{k,l}_i)
+ *   Y_dev[i][r] = exp(I_i) sum_{c : j*_c > i} D^c_{j*_c}     (the pathwise loss xi^{k,l}_i)
+ * X_dev [n+1][d + C][n_b M] and Y_dev [n+1][n_b M] are float; features_dev [n+1][d][M] and D_dev
+ * as hsim_outer_paths of the same precision (d = 0: indicators only).  M * n_b <= 2^31.  The
+ * rows feed cva_regress_fit with M' = n_b M rows and n_feat = d + C (the network takes at most
+ * 32 inputs).  No workspace. */
+int hsim_sample_rows(const hsim_grid* grid, int32_t n_cpty, int32_t d, uint64_t seed,
+                     int64_t path_begin, int64_t M, int32_t n_b, int precision,
+                     const void* features_dev, const double* I_dev, const double* Lambda_dev,
+                     const void* D_dev, float* X_dev, float* Y_dev, void* stream);
+
 /* Grouped per-inner-sample targets for one counterparty (Section 3.2 with X the default
  * indicator; Algorithm 1's loss over all (path, draw) samples).  A draw whose client has
  * defaulted by t_i has nothing left to lose, and over the A_i draws still alive at t_i the sum

@@ -474,6 +474,42 @@ int hsim_targets_cva(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b,
                                    target_dev, cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream);
 }
 
+int hsim_sample_rows(const hsim_grid* g, int32_t n_cpty, int32_t d, uint64_t seed, int64_t path_begin, int64_t M,
+                     int32_t n_b, int precision, const void* features_dev, const double* I_dev,
+                     const double* Lambda_dev, const void* D_dev, float* X_dev, float* Y_dev, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if ((rc = check_precision(precision))) return rc;
+  if ((rc = check_paths(path_begin, M))) return rc;
+  if (n_cpty < 1 || n_cpty > HSIM_MAX_CPTY) return fail(HSIM_ERANGE, "n_cpty out of range");
+  if (d < 0 || d > 4096) return fail(HSIM_EINVAL, "bad feature count %d", d);
+  if (n_b < 1 || n_b > (1 << 24)) return fail(HSIM_ERANGE, "n_b %d outside [1, 2^24]", n_b);
+  if (M * (int64_t)n_b > ((int64_t)1 << 31)) return fail(HSIM_ERANGE, "M * n_b exceeds 2^31 samples");
+  if ((d > 0 && !features_dev) || !I_dev || !Lambda_dev || !D_dev || !X_dev || !Y_dev)
+    return fail(HSIM_EINVAL, "NULL array");
+  auto run = [&](auto tag) -> int {
+    using Real = decltype(tag);
+    SampleArgs<Real> a;
+    a.M = M;
+    a.path_begin = (uint32_t)path_begin;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.n_dates = g->n_dates;
+    a.n_cpty = n_cpty;
+    a.d = d;
+    a.n_b = n_b;
+    a.features = (const Real*)features_dev;
+    a.I = I_dev;
+    a.Lam = Lambda_dev;
+    a.D = (const Real*)D_dev;
+    a.X = X_dev;
+    a.Y = Y_dev;
+    const hipError_t e = launch_sample_rows<Real>(a, (hipStream_t)stream);
+    return e == hipSuccess ? HSIM_OK : device_error(e, "sample rows launch");
+  };
+  return precision == HSIM_FP32 ? run(0.0f) : run(0.0);
+}
+
 int hsim_targets_alive(const hsim_grid* g, int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
                        int precision, const double* I_dev, const void* D_dev, const int32_t* counts_dev,
                        void* target_dev, float* weight_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,

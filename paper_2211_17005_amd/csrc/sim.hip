@@ -323,6 +323,14 @@ __global__ __launch_bounds__(kTargetBlock) void branch_stats_kernel(int64_t M, i
 // ------------------------------------------------------------------------------------
 // inner default draws
 // ------------------------------------------------------------------------------------
+// Threshold form of the default rule on the 23-bit uniform u = (2m+1) 2^-24:
+//   Lambda >= -log u  <=>  u >= exp(-Lambda)  <=>  m >= ceil((exp(-Lambda) 2^24 - 1) / 2).
+__device__ __forceinline__ uint32_t default_threshold(double lam) {
+  const double S = exp(-lam);
+  const double t = ceil((S * 16777216.0 - 1.0) * 0.5);
+  return t <= 0.0 ? 0u : (uint32_t)t;
+}
+
 // The draws of one tile of 64 paths (one lane per path).
 __device__ void inner_tile(const InnerArgs& a, uint32_t* lds, int64_t tile) {
   const int lane = threadIdx.x;
@@ -340,12 +348,7 @@ __device__ void inner_tile(const InnerArgs& a, uint32_t* lds, int64_t tile) {
     // Threshold form of the default rule: with u = (2m+1) 2^-24,
     //   Lambda_j >= -log u  <=>  u >= exp(-Lambda_j)  <=>  m >= ceil((exp(-Lambda_j) 2^24 - 1)/2).
     for (int j = 0; j <= n; ++j) {
-      uint32_t th = 0xFFFFFFFFu;
-      if (valid) {
-        const double S = exp(-a.Lam[((int64_t)j * C + c) * M + kl]);
-        const double t = ceil((S * 16777216.0 - 1.0) * 0.5);
-        th = t <= 0.0 ? 0u : (uint32_t)t;
-      }
+      const uint32_t th = valid ? default_threshold(a.Lam[((int64_t)j * C + c) * M + kl]) : 0xFFFFFFFFu;
       K[j * kInnerBlock + lane] = th;
       cnt[j * kInnerBlock + lane] = 0u;
     }
@@ -391,6 +394,56 @@ __global__ __launch_bounds__(kInnerBlock) void inner_kernel(const InnerArgs a) {
     t = __shfl(t, 0);
     if (t >= tiles) break;
     inner_tile(a, lds, a.order[t]);
+  }
+}
+
+// Per-inner-sample regression rows: one lane per sample (draw l, path k), row r = l M + k (the
+// order whose contiguous slices are the paper's minibatches).  The draw is the inner kernel's
+// (same Philox word, same threshold rule); its default date per counterparty comes from a
+// binary search on the thresholds of Lambda^c, and at every date i the row holds the path's
+// market features, the indicators 1{j*_c <= i} and the label
+//   xi_i = exp(I_i) sum_{c : j*_c > i} D^c_{j*_c}.
+template <typename Real>
+__global__ __launch_bounds__(kTargetBlock) void sample_rows_kernel(const SampleArgs<Real> a) {
+  const int64_t r = (int64_t)blockIdx.x * kTargetBlock + threadIdx.x;
+  const int64_t M = a.M;
+  if (r >= M * a.n_b) return;
+  const int64_t kl = r % M;
+  const uint32_t l = (uint32_t)(r / M);
+  const uint32_t k = a.path_begin + (uint32_t)kl;
+  const int n = a.n_dates, C = a.n_cpty, d = a.d;
+  const int64_t R = M * a.n_b;
+  int js[kMaxCpty];
+  double dv[kMaxCpty];                      // D^c at the default date (0 without default)
+#pragma unroll
+  for (int c = 0; c < kMaxCpty; ++c) {
+    js[c] = n + 1;
+    dv[c] = 0.0;
+    if (c >= C) continue;
+    const u32x4 w = philox4x32_10(k, l >> 2, (uint32_t)c, kTagInner, a.key0, a.key1);
+    const uint32_t word = (l & 3) == 0 ? w.x : (l & 3) == 1 ? w.y : (l & 3) == 2 ? w.z : w.w;
+    const uint32_t m = grid23(word);
+    if (m >= default_threshold(a.Lam[((int64_t)n * C + c) * M + kl])) {   // defaults by the horizon
+      int lo = 1, hi = n;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (m >= default_threshold(a.Lam[((int64_t)mid * C + c) * M + kl])) hi = mid; else lo = mid + 1;
+      }
+      js[c] = lo;
+      dv[c] = (double)a.D[((int64_t)lo * C + c) * M + kl];
+    }
+  }
+  for (int i = 0; i <= n; ++i) {
+    float* X = a.X + (int64_t)i * (d + C) * R + r;
+    for (int f = 0; f < d; ++f) X[(int64_t)f * R] = (float)a.features[((int64_t)i * d + f) * M + kl];
+    double S = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxCpty; ++c) {
+      if (c >= C) continue;
+      X[(int64_t)(d + c) * R] = js[c] <= i ? 1.0f : 0.0f;
+      if (js[c] > i) S += dv[c];
+    }
+    a.Y[(int64_t)i * R + r] = (float)(S * exp(a.I[(int64_t)i * M + kl]));
   }
 }
 
@@ -573,6 +626,15 @@ hipError_t launch_inner(const InnerArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL(inner_kernel, dim3(grid), dim3(kInnerBlock), lds, stream, a);
   return hipGetLastError();
 }
+
+template <typename Real>
+hipError_t launch_sample_rows(const SampleArgs<Real>& a, hipStream_t stream) {
+  const int64_t nblk = (a.M * a.n_b + kTargetBlock - 1) / kTargetBlock;
+  hipLaunchKernelGGL((sample_rows_kernel<Real>), dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, a);
+  return hipGetLastError();
+}
+template hipError_t launch_sample_rows<float>(const SampleArgs<float>&, hipStream_t);
+template hipError_t launch_sample_rows<double>(const SampleArgs<double>&, hipStream_t);
 
 template <typename Real>
 hipError_t launch_branch(const SimArgs<Real>& a, const BranchArgs& b, hipStream_t stream) {

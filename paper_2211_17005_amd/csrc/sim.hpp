@@ -81,6 +81,21 @@ struct TargetArgs {
   double* cva0;                      // one double
 };
 
+// Per-inner-sample regression rows (market state + default indicators) of M x n_b samples.
+template <typename Real>
+struct SampleArgs {
+  int64_t M;
+  uint32_t path_begin;
+  uint32_t key0, key1;
+  int32_t n_dates, n_cpty, d, n_b;
+  const Real* features;              // [n+1][d][M]
+  const double* I;                   // [n+1][M]
+  const double* Lam;                 // [n+1][C][M]
+  const Real* D;                     // [n+1][C][M]
+  float* X;                          // [n+1][d + C][n_b M]
+  float* Y;                          // [n+1][n_b M]
+};
+
 // Branched re-simulation: continuations b < n_branch of every path after pricing date `date`.
 struct BranchArgs {
   int32_t date;
@@ -115,6 +130,8 @@ template <typename Real>
 hipError_t launch_targets(const TargetArgs<Real>& a, hipStream_t stream);
 template <typename Real>
 hipError_t launch_branch(const SimArgs<Real>& a, const BranchArgs& b, hipStream_t stream);
+template <typename Real>
+hipError_t launch_sample_rows(const SampleArgs<Real>& a, hipStream_t stream);
 // Workspace of launch_branch_stats (FP64 block partials of the kBranchStats statistics).
 size_t branch_stats_bytes(int64_t M);
 // out[kBranchStats] = path means of the statistics; phi may be null (phi = 0).

@@ -97,6 +97,8 @@ def lib():
         "cva_regress_workspace_bytes": (sz, [ctypes.POINTER(MlpCfg), i32, i64]),
         "cva_regress_fit": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32, vp,
                                            vp, vp, u64, vp, vp, vp, sz, vp]),
+        "hsim_sample_rows": (ctypes.c_int, [G_, i32, i32, u64, i64, i64, i32, ctypes.c_int, vp, vp, vp,
+                                            vp, vp, vp, vp]),
         "hsim_targets_alive": (ctypes.c_int, [G_, i64, i32, vp, i32, ctypes.c_int, vp, vp, vp, vp, vp,
                                               vp, vp, sz, vp]),
         "cva_regress_predict": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32,
@@ -314,6 +316,25 @@ def targets_cva(grid, n_cpty: int, I, D, counts, n_b: int = 1, n_b_per_block=Non
                                  _dptr(ws), wsb, _stream()))
     torch.cuda.current_stream().synchronize() if nbt is not None else None
     return T, cva0
+
+
+def sample_rows(w, out, n_b: Optional[int] = None, precision: int = HSIM_FP32, path_begin: int = 0):
+    """hsim_sample_rows on the outputs `out` of outer_paths (same precision and path range):
+    X [n+1][d + C][n_b M], Y [n+1][n_b M] float32 device tensors."""
+    import torch
+    n_b = w.n_b if n_b is None else n_b
+    I = out["I"]
+    n1, M = I.shape
+    C = out["Lam"].shape[1]
+    feats = out["features"]
+    d = 0 if feats is None else int(feats.shape[1])
+    X = torch.empty((n1, d + C, n_b * M), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n1, n_b * M), dtype=torch.float32, device="cuda")
+    g = grid_struct(w.grid)
+    check(lib().hsim_sample_rows(ctypes.byref(g), C, d, w.seed, path_begin, M, n_b, precision,
+                                 _dptr(feats), _dptr(I), _dptr(out["Lam"]), _dptr(out["D"]), _dptr(X),
+                                 _dptr(Y), _stream()))
+    return X, Y
 
 
 def targets_alive(grid, I, D, counts, n_b: int = 1, n_b_per_block=None, block_paths: int = 64,

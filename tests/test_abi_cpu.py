@@ -181,3 +181,15 @@ def test_branch_entry_points_reject_bad_arguments(hs, cpu_only):
     assert e(1000, 1, 1, None, dummy, dummy, dummy, need, None) == -2   # B < 2
     assert e(1000, 2, 1, None, dummy, dummy, dummy, need - 1, None) == -3
     assert e(0, 2, 1, None, dummy, dummy, dummy, need, None) == -1
+
+
+def test_sample_rows_reject_bad_arguments(hs, cpu_only):
+    g = hs.grid_struct(wl.Grid(10.0, 50, 25))
+    dummy = ctypes.c_void_p(256)
+    f = hs.lib().hsim_sample_rows
+    ok = (dummy, dummy, dummy, dummy, dummy, dummy, None)
+    assert f(ctypes.byref(g), 0, 2, 0, 0, 64, 4, 1, *ok) == -2            # n_cpty
+    assert f(ctypes.byref(g), 1, 2, 0, 0, 64, 0, 1, *ok) == -2            # n_b
+    assert f(ctypes.byref(g), 1, 2, 0, 0, 1 << 28, 16, 1, *ok) == -2      # M n_b > 2^31
+    assert f(ctypes.byref(g), 1, 2, 0, 0, 64, 4, 1, None, dummy, dummy, dummy, dummy, dummy,
+             None) == -1                                                  # features

@@ -1,0 +1,111 @@
+"""The paper's per-inner-sample regression rows (hsim_sample_rows) and the regression on them,
+through the C ABI, against the FP64 oracle.
+
+Tolerances: default indicators bit-exact in FP64 mode (the same threshold rule as the inner
+draws; in FP32 mode they equal the rule applied to the GPU's own Lambda); labels to float
+rounding (1e-6 scale-relative) in FP64 mode and 1e-5 in FP32 mode on samples whose default dates
+agree; market inputs exact copies.  The fit on the rows is held to the BF16 regression bar
+(2e-2 relative L2) in the configuration where the FP64 fit itself moves by less than 1 % under
+BF16-sized input perturbations (one hidden layer, batches of 512 samples, 4 epochs); the
+single-draw labels make longer runs more trajectory-sensitive.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import inner as oinner
+from oracle import model, pipeline
+from oracle import regression as org
+
+pytestmark = pytest.mark.gpu
+
+
+def npy(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_rows(w):
+    paths = np.arange(w.M)
+    o = model.simulate_outer(w, paths)
+    mt = model.mtm(w, o)
+    u = oinner.inner_draws(w, paths)
+    js = oinner.default_dates(o.Lam, u)
+    xi = oinner.pathwise_loss(o.I, mt, w.market.lgd, js)
+    F = model.features(w, o)
+    X, Y = oinner.sample_rows(F, xi, js)
+    return X, Y, js
+
+
+@pytest.fixture(scope="module")
+def multi():
+    w = wl.small_multi(M=77, n_b=5)                           # ragged block of 256 samples
+    return w, oracle_rows(w)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_rows_match_oracle(lib, multi, precision):
+    w, (Xr, Yr, js) = multi
+    out = lib.outer_paths(w, precision=precision)
+    X, Y = lib.sample_rows(w, out, precision=precision)
+    X, Y = npy(X).astype(np.float64), npy(Y).astype(np.float64)
+    d, C, P = out["features"].shape[1], w.market.n_cpty, w.M
+    F = npy(out["features"]).astype(np.float32).astype(np.float64)
+    for l in range(w.n_b):                                    # market inputs: the path's own
+        assert np.array_equal(X[:, :d, l * P:(l + 1) * P], F)
+    if precision == 0:
+        assert np.array_equal(X[:, d:], Xr[:, d:])
+        err = np.max(np.abs(Y - Yr)) / np.max(np.abs(Yr))
+        print(f"  FP64 labels: err {err:.3e}")
+        assert err <= 1e-6
+        return
+    # FP32: indicators are the rule on the GPU's own Lambda
+    u = oinner.inner_draws(w, np.arange(P))
+    Lg = np.transpose(npy(out["Lam"]), (0, 2, 1))
+    jg = oinner.default_dates(Lg, u)                          # [P, n_b, C]
+    n = w.grid.n_dates
+    ind = (jg.transpose(1, 2, 0).reshape(w.n_b, C, P)[None] <= np.arange(n + 1)[:, None, None, None])
+    ind = ind.transpose(0, 2, 1, 3).reshape(n + 1, C, w.n_b * P)
+    assert np.array_equal(X[:, d:], ind.astype(np.float64))
+    same = np.all(jg == js, axis=2).T.reshape(-1)             # samples whose default dates agree
+    err = np.max(np.abs(Y[:, same] - Yr[:, same])) / np.max(np.abs(Yr))
+    print(f"  FP32 labels: err {err:.3e} on {same.mean():.4f} of the samples")
+    assert same.mean() > 0.99 and err <= 1e-5
+
+
+def test_rows_agree_with_counts_and_targets(lib):
+    w = wl.small_multi(M=300, n_b=12)
+    out = lib.outer_paths(w, precision=0)
+    X, Y = lib.sample_rows(w, out, precision=0)
+    cnt = npy(lib.inner_defaults(w.grid, w.market.n_cpty, w.seed, out["Lam"], n_b=w.n_b))
+    T, _ = lib.targets_cva(w.grid, w.market.n_cpty, out["I"], out["D"],
+                           lib.inner_defaults(w.grid, w.market.n_cpty, w.seed, out["Lam"], n_b=w.n_b),
+                           n_b=w.n_b, precision=0)
+    X, Y = npy(X), npy(Y).astype(np.float64)
+    n, C, P, d = w.grid.n_dates, w.market.n_cpty, w.M, out["features"].shape[1]
+    inc = np.diff(X[:, d:], axis=0).reshape(n, C, w.n_b, P).sum(axis=2)
+    assert np.array_equal(inc.astype(np.int64), cnt[1:].astype(np.int64))
+    avg = Y.reshape(n + 1, w.n_b, P).mean(axis=1)
+    Tn = npy(T)
+    assert np.max(np.abs(avg - Tn)) <= 1e-6 * np.max(np.abs(Tn))
+
+
+def test_literal_regression_on_the_rows_matches_oracle(lib):
+    import torch
+    w = wl.small_multi(M=512, n_b=8)
+    Xr, Yr, _ = oracle_rows(w)
+    out = lib.outer_paths(w, precision=0)
+    X, Y = lib.sample_rows(w, out, precision=0)
+    dates = [3, 10, 15]
+    mlp = wl.MLPConfig(hidden=1, width=32, epochs=4, batch=512)
+    cfg = lib.mlp_cfg(mlp, X.shape[1], X.shape[2])
+    model_, loss, _ = lib.regress_fit(cfg, dates, X, Y, seed=w.seed)
+    pred = npy(lib.regress_predict(cfg, dates, X, model_)).astype(np.float64)
+    fits = org.independent_fits(Xr.astype(np.float32).astype(np.float64),
+                                Yr.astype(np.float32).astype(np.float64), mlp, w.seed, dates)
+    for j, i in enumerate(dates):
+        p64 = org.predict(fits[i], Xr[i].T.astype(np.float32).astype(np.float64))
+        l2 = np.linalg.norm(pred[j] - p64) / np.linalg.norm(p64)
+        print(f"  date {i}: l2 {l2:.3e}; loss gpu {npy(loss)[j][-1]:.5f} fp64 {fits[i].losses[-1]:.5f}",
+              flush=True)
+        assert l2 <= 2e-2
+        assert npy(loss)[j][-1] == pytest.approx(fits[i].losses[-1], rel=1e-2)
