@@ -67,6 +67,20 @@ def outer_ops_per_path(w) -> dict:
     return {"substep": sub, "total": S * sub + price}
 
 
+def branch_ops_per_lane(w, date: int) -> float:
+    """Algorithmic VALU operations of one lane of the branched re-simulation: every Euler
+    sub-step of the horizon (the outer prefix up to `date`, the continuation after it) and the
+    pricing of the dates after `date` (the op counts of outer_ops_per_path)."""
+    m = w.market
+    n_e, C = m.n_ccy, m.n_cpty
+    sub = outer_ops_per_path(w)["substep"]
+    q = int(round(w.grid.n_dates * w.portfolio.delta / w.grid.horizon))
+    P = int(np.max(w.portfolio.maturity))
+    price = sum(max(0, P - (i // q)) * n_e * (2 + C) + n_e * (3 + 4 * C)
+                for i in range(date + 1, w.grid.n_dates + 1))
+    return w.grid.n_dates * w.grid.n_sub * sub + price
+
+
 def mlp_flops_per_date(d_in: int, width: int, hidden: int, M: int, epochs: int) -> float:
     """Algorithmic FLOPs of BaseAlg on one date (FMA = 2).
 
@@ -275,8 +289,12 @@ def validation(hsim, torch, w, cfg, model, dates, date: int = 50, paths: int = 1
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         st = hsim.branch_errors(xi, phi)
+        ops = branch_ops_per_lane(w, date) * paths * B
         out[tag] = {"branches": B, "ms": ms,
                     "lane_steps_per_s": paths * B * w.grid.n_dates * w.grid.n_sub / (ms / 1e3),
+                    "roofline": {"bound": "alu", "kernel": "branch_kernel<float,10,8>",
+                                 "achieved": ops / (ms / 1e3) / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                                 "unit": "T VALU lane-ops/s", "frac": ops / (ms / 1e3) / VALU_PEAK_OPS},
                     "rel_l2_twin": float(np.sqrt(max(st["mse_twin"], 0.0) / st["cva_sq"])),
                     "rel_l2_vs_nested": float(np.sqrt(st["mse_nested"] / st["cva_sq_nested"])),
                     "cva_mean": st["cva_mean"], "phi_mean": st["phi_mean"]}
