@@ -248,16 +248,34 @@ struct DwMap {
   static_assert(BO * BI == TW && NIB * NOB * TW == NT * KT && NIB * NOB <= kMlpWaves, "tiling");
 };
 
+// Weights of layer l from FP32 global memory into the BF16 LDS copy: each thread issues the
+// loads of kLoadBatch elements before it stores any of them (the copy is latency-bound otherwise).
+template <int U, int H, int l>
+__device__ __forceinline__ void load_layer_weights(const Smem<U, H>& S, const float* __restrict__ src, int t) {
+  constexpr int K = Smem<U, H>::ldk(l), SWl = Smem<U, H>::lds(l);
+  constexpr int PER = U * K / kMlpThreads, kLoadBatch = PER < 8 ? PER : 8;
+  static_assert(PER * kMlpThreads == U * K && PER % kLoadBatch == 0, "whole batches per thread");
+  __bf16* W = S.W(l);
+  for (int i0 = 0; i0 < PER; i0 += kLoadBatch) {
+    float v[kLoadBatch];
+#pragma unroll
+    for (int i = 0; i < kLoadBatch; ++i) v[i] = src[t + (i0 + i) * kMlpThreads];
+#pragma unroll
+    for (int i = 0; i < kLoadBatch; ++i) {
+      const int e = t + (i0 + i) * kMlpThreads;
+      W[lidx(e / K, e % K, SWl)] = (__bf16)v[i];
+    }
+  }
+}
+
 // Copy the FP32 parameters of one network into the workgroup's BF16 / FP32 LDS copies.
 template <int U, int H>
 __device__ void load_weights(const Smem<U, H>& S, const float* P, const MlpLayout& L) {
-  for (int l = 1; l <= H; ++l) {
-    const int K = S.ldk(l), SWl = S.lds(l);
-    __bf16* W = S.W(l);
-    const float* src = P + L.w_off(l);
-    for (int e = opaque_tid(); e < U * K; e += kMlpThreads) W[lidx(e / K, e % K, SWl)] = (__bf16)src[e];
+  load_layer_weights<U, H, 1>(S, P + L.w_off(1), opaque_tid());
+  if constexpr (H >= 2) load_layer_weights<U, H, 2>(S, P + L.w_off(2), opaque_tid());
+  if constexpr (H >= 3) load_layer_weights<U, H, 3>(S, P + L.w_off(3), opaque_tid());
+  for (int l = 1; l <= H; ++l)
     for (int e = opaque_tid(); e < U; e += kMlpThreads) S.bias(l)[e] = P[L.b_off(l) + e];
-  }
   for (int e = opaque_tid(); e < U; e += kMlpThreads) S.wout()[e] = P[L.wout_off() + e];
   if (opaque_tid() == 0) {
     S.scal()[0] = P[L.bout_off()];
@@ -622,8 +640,9 @@ __device__ void backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, 
 constexpr int kTeamSpinLimit = 1 << 22;   // polls before a team barrier gives up (several seconds)
 
 // Barrier of the G workgroups of a team: a monotonic arrival counter in global memory.  Every
-// thread publishes its global writes at device scope before its workgroup arrives; after the
-// wait every wave invalidates its stale cached lines.  All workgroups of a launch are resident
+// wave waits for its global stores to complete, the workgroup's arrival (an agent-scope release)
+// publishes them; the arriving thread polls the counter without ordering, acquires once when it
+// is reached, and after the barrier every wave invalidates its stale cached lines.  All workgroups of a launch are resident
 // (cooperative launch), so the wait ends; should it not within the poll limit, the workgroup
 // marks itself failed, stops waiting at later barriers (it still arrives) and leaves the fit at
 // the end of the epoch with a NaN loss, so a launch always terminates.
@@ -636,7 +655,10 @@ struct Team {
       __syncthreads();
       return;
     }
-    __threadfence();
+    // every wave's global stores have completed before the barrier; the one agent-scope release
+    // of the arrival then publishes them all (a per-wave device fence would write the L2 back
+    // once per wave)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     ++arrivals;
     __shared__ int s_failed;
@@ -644,13 +666,16 @@ struct Team {
       __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       const int target = arrivals * G;
       int polls = failed ? kTeamSpinLimit : 0;
+      // relaxed polls (an acquiring poll would invalidate the cache on every iteration), one
+      // acquire fence once the count is reached
       while (polls < kTeamSpinLimit &&
-             __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+             __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(2);
         ++polls;
       }
       s_failed = polls == kTeamSpinLimit &&
-                 __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target;
+                 __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     failed = failed || s_failed;
@@ -785,12 +810,37 @@ __device__ void team_step(const Smem<U, H>& S, const MlpArgs& a, Team& tm, int t
     S.scal()[3] = 0.0f;
   }
   tm.sync();
-  const float* part0 = a.partial + (int64_t)team * tm.G * NP;
+  // this member's slice of the parameters: the loads of kAdamBatch elements per thread are issued
+  // before any of them is used (restrict views: the stores of a batch do not alias the next loads)
+  const float* __restrict__ part0 = a.partial + (int64_t)team * tm.G * NP;
+  float* __restrict__ Pr = P;
+  float* __restrict__ Mr = Mm;
+  float* __restrict__ Vr = Vv;
   const int lo = (int)((int64_t)NP * tm.member / tm.G), hi = (int)((int64_t)NP * (tm.member + 1) / tm.G);
-  for (int p = lo + opaque_tid(); p < hi; p += kMlpThreads) {
-    float g = 0.0f;
-    for (int j = 0; j < tm.G; ++j) g += part0[(int64_t)j * NP + p];
-    P[p] = st(P[p], g, &Mm[p], &Vv[p]);
+  constexpr int kAdamBatch = 8;
+  for (int p0 = lo + opaque_tid(); p0 < hi; p0 += kMlpThreads * kAdamBatch) {
+    float g[kAdamBatch], pv[kAdamBatch], mv[kAdamBatch], vv[kAdamBatch];
+#pragma unroll
+    for (int u = 0; u < kAdamBatch; ++u) {
+      const int q = p0 + u * kMlpThreads;
+      g[u] = pv[u] = mv[u] = vv[u] = 0.0f;
+      if (q < hi) {
+        for (int j = 0; j < tm.G; ++j) g[u] += part0[(int64_t)j * NP + q];
+        pv[u] = Pr[q];
+        mv[u] = Mr[q];
+        vv[u] = Vr[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kAdamBatch; ++u) {
+      const int q = p0 + u * kMlpThreads;
+      if (q < hi) {
+        const float np = st(pv[u], g[u], &mv[u], &vv[u]);
+        Pr[q] = np;
+        Mr[q] = mv[u];
+        Vr[q] = vv[u];
+      }
+    }
   }
   tm.sync();
   load_weights<U, H>(S, P, L);
