@@ -918,7 +918,10 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
   for (int s = 0; s < GS; ++s)
 #pragma unroll
     for (int v = 0; v < 4; ++v) accG[s][v] = 0.0;
-  // thread u: sum w h_u, sum w h_u (y - mu); thread U: sum w (y - mu), sum w
+  // thread t, column u = t % U, row group t / U of the chunk: sum w h_u, sum w h_u (y - mu); the
+  // threads of column 0 also sum w (y - mu) and w.  Groups are combined in a fixed order below.
+  constexpr int NGRP = kMlpThreads / U;
+  static_assert(NGRP * U == kMlpThreads && 2 * kMlpThreads * 8 <= Smem<U, H>::red_bytes, "column groups");
   double hs = 0.0, hy = 0.0, ys = 0.0, sw = 0.0;
   const float mu = S.scal()[1];
   const int64_t stride = (int64_t)R * tm.G, first = (int64_t)R * tm.member;
@@ -956,20 +959,21 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) accG[s][v] += (double)part[v];
     }
-    if (tid < U) {
+    {
+      const int u = tid % U, grp = tid / U;
 #pragma unroll 1
-      for (int r = 0; r < n; ++r) {
+      for (int r = grp; r < n; r += NGRP) {
         // with weights the stored row is sqrt(w) h: one more sqrt(w) gives w h
-        const double h = (double)(float)Hh[lidx(r, tid, Smem<U, H>::SW)] * (weighted ? sqrt((double)S.wbuf()[r]) : 1.0);
+        const double h = (double)(float)Hh[lidx(r, u, Smem<U, H>::SW)] * (weighted ? sqrt((double)S.wbuf()[r]) : 1.0);
         hs += h;
         hy += h * (double)(S.ybuf()[r] - mu);
       }
-    } else if (tid == U) {
-      for (int r = 0; r < n; ++r) {
-        const double w = S.wbuf()[r];
-        ys += w * (double)(S.ybuf()[r] - mu);
-        sw += w;
-      }
+      if (u == 0)
+        for (int r = grp; r < n; r += NGRP) {
+          const double w = S.wbuf()[r];
+          ys += w * (double)(S.ybuf()[r] - mu);
+          sw += w;
+        }
     }
     __syncthreads();
   }
@@ -983,13 +987,37 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
     for (int v = 0; v < 4; ++v) G[(16 * ot + 4 * (lane / 16) + v) * N + 16 * it + lane % 16] = accG[s][v];
   }
   double* rhs = G + N * N;
-  if (tid < U) {
-    G[tid * N + U] = hs;
-    G[U * N + tid] = hs;
-    rhs[tid] = hy;
-  } else if (tid == U) {
-    G[U * N + U] = sw;
-    rhs[U] = ys;
+  {
+    double* red = (double*)S.red();
+    const int u = tid % U, grp = tid / U;
+    red[grp * 2 * U + u] = hs;
+    red[grp * 2 * U + U + u] = hy;
+    __syncthreads();
+    if (tid < U) {
+      double a = 0.0, b = 0.0;
+      for (int g = 0; g < NGRP; ++g) {
+        a += red[g * 2 * U + tid];
+        b += red[g * 2 * U + U + tid];
+      }
+      G[tid * N + U] = a;
+      G[U * N + tid] = a;
+      rhs[tid] = b;
+    }
+    __syncthreads();
+    if (u == 0) {
+      red[2 * grp] = ys;
+      red[2 * grp + 1] = sw;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int g = 0; g < NGRP; ++g) {
+        a += red[2 * g];
+        b += red[2 * g + 1];
+      }
+      G[U * N + U] = b;
+      rhs[U] = a;
+    }
   }
   tm.sync();
   if (tm.member != 0) {                 // the first workgroup solves; the others wait for w_out
