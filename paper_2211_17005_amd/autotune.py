@@ -4,9 +4,12 @@ The one free launch parameter that matters is the regression team size: how many
 train one date together (the batch gradient summed across them, Adam sharded over them).  More
 workgroups per date shorten every SGD step but cost a cross-workgroup exchange per step and
 leave fewer teams for the other dates; the best size depends on the number of dates, the batch,
-the network and the device.  `regression_team` times one epoch of the actual fit for each
-candidate size and keeps the fastest; the choice is cached in JSON keyed by (device, shape), so
-a cached run is deterministic and costs nothing.  The cache file is `tuned.json` beside this
+the network, the number of epochs and the device.  `regression_team` times the actual fit with
+one and with three epochs for each candidate size, extrapolates linearly to the configured
+number of epochs (a fit has per-date costs that do not scale with the epochs: statistics, the
+last epoch's losses when workgroups without a team compute them) and keeps the fastest; the
+choice is cached in JSON keyed by (device, shape), so a cached run is deterministic and costs
+nothing.  The cache file is `tuned.json` beside this
 module unless HSIM_TUNE_CACHE names another path.
 """
 from __future__ import annotations
@@ -47,13 +50,14 @@ def device_key() -> str:
 
 def regression_key(cfg, n_dates: int, M: int) -> str:
     return (f"{device_key()}|regress|U{cfg.width}H{cfg.hidden}d{cfg.d_in}|batch{cfg.batch}"
-            f"|M{M}|dates{n_dates}|warm{cfg.warm_start}")
+            f"|epochs{cfg.epochs}|M{M}|dates{n_dates}|warm{cfg.warm_start}")
 
 
 def regression_team(cfg, dates, X, Y, seed: int = 0, candidates=CANDIDATES, force: bool = False,
                     reps: int = 2) -> int:
     """Team size for fitting `dates` of X / Y with `cfg` (a hsim.MlpCfg): the cached choice, or
-    the fastest candidate over one epoch of the real fit (min of `reps` runs)."""
+    the candidate with the least extrapolated time t(1) + (E - 1) (t(3) - t(1)) / 2 of the real
+    fit (each timing the min of `reps` runs)."""
     import torch
     from . import hsim
     n_dates = len(dates)
@@ -63,25 +67,31 @@ def regression_team(cfg, dates, X, Y, seed: int = 0, candidates=CANDIDATES, forc
     if key in cache and not force:
         return int(cache[key]["team"])
     chunks = -(-cfg.batch // 64)
+    E = int(cfg.epochs)
     times = {}
     for team in candidates:
         if team > max(1, chunks):
             continue
-        trial = hsim.MlpCfg(cfg.hidden, cfg.width, cfg.d_in, 1, cfg.batch, cfg.lr, cfg.beta1,
-                            cfg.beta2, cfg.eps, cfg.warm_start, cfg.init_tag, team)
-        if hsim.lib().cva_regress_workspace_bytes(ctypes.byref(trial), n_dates, M) == 0:
-            continue                                   # does not fit on the device
-        best = float("inf")
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            hsim.regress_fit(trial, dates, X, Y, seed=seed, want_loss=False)
-            torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t)
-        times[team] = best
+        t_e = {}
+        for epochs in ((1, 3) if E > 1 else (1,)):
+            trial = hsim.MlpCfg(cfg.hidden, cfg.width, cfg.d_in, epochs, cfg.batch, cfg.lr, cfg.beta1,
+                                cfg.beta2, cfg.eps, cfg.warm_start, cfg.init_tag, team)
+            if hsim.lib().cva_regress_workspace_bytes(ctypes.byref(trial), n_dates, M) == 0:
+                break                                  # does not fit on the device
+            best = float("inf")
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                hsim.regress_fit(trial, dates, X, Y, seed=seed, want_loss=False)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t)
+            t_e[epochs] = best
+        if 1 not in t_e or (E > 1 and 3 not in t_e):
+            continue
+        times[team] = t_e[1] + (E - 1) * (t_e[3] - t_e[1]) / 2.0 if E > 1 else t_e[1]
     if not times:
         raise RuntimeError("no team size fits on the device for this regression")
     team = min(times, key=lambda t: (times[t], t))
-    cache[key] = {"team": team, "epoch_ms": {str(k): round(v * 1e3, 3) for k, v in times.items()}}
+    cache[key] = {"team": team, "fit_ms": {str(k): round(v * 1e3, 3) for k, v in times.items()}}
     _save(cache)
     return team

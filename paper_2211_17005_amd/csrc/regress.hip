@@ -880,6 +880,9 @@ __device__ float full_loss(const Smem<U, H>& S, const Lanes& ln, const Feeder& f
       const float d = fmaxf(output_of_row<U, H>(S, t), 0.0f) + S.scal()[1] - y.y;
       e += (double)y.w * (double)d * (double)d;
     }
+    // with one hidden layer the next chunk's only layer writes the output partials at once: wait
+    // until they have been read (deeper networks wait at their first layer's barrier)
+    if constexpr (H == 1) __syncthreads();
     y = y_next;
     parity ^= 1;
   }
@@ -1098,6 +1101,118 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
 // ------------------------------------------------------------------------------------------
 // BaseAlg for one date
 // ------------------------------------------------------------------------------------------
+// ------------------------------------------------------------------------------------------
+// loss helpers: the full-sample loss of each epoch off the teams' critical path
+// ------------------------------------------------------------------------------------------
+// The loss only decides which epoch's parameters are kept (Algorithm 1's best tracking), never
+// the training itself, so a team publishes a snapshot of its parameters after every epoch and
+// goes on; workgroups without a team (and teams that are done) compute the losses, and the
+// helper that computes a date's last loss keeps the first epoch of least loss.
+constexpr int kReadySkip = -2;    // untrained date: loss 0, no selection
+constexpr int kReadyFail = -1;    // failed team: loss NaN
+
+__device__ __forceinline__ void mark_epochs(const MlpArgs& a, int job, int e0, int value) {
+  for (int e = e0; e < a.epochs; ++e)
+    __hip_atomic_exchange(a.ready + (int64_t)job * a.epochs + e, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// This member's slice of the parameters into the snapshot of `epoch` (1-based), then its arrival.
+__device__ void publish_snapshot(const MlpArgs& a, int job, int epoch, const float* P, int NP, const Team& tm) {
+  float* __restrict__ dst = a.snaps + ((int64_t)job * a.epochs + epoch - 1) * NP;
+  const float* __restrict__ src = P;
+  const int lo = (int)((int64_t)NP * tm.member / tm.G), hi = (int)((int64_t)NP * (tm.member + 1) / tm.G);
+  constexpr int kBatch = 8;
+  for (int p0 = lo + opaque_tid(); p0 < hi; p0 += kMlpThreads * kBatch) {
+    float v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) v[u] = p0 + u * kMlpThreads < hi ? src[p0 + u * kMlpThreads] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (p0 + u * kMlpThreads < hi) dst[p0 + u * kMlpThreads] = v[u];
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(a.ready + (int64_t)job * a.epochs + epoch - 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int U, int H>
+__device__ void loss_helper(const Smem<U, H>& S, const MlpArgs& a) {
+  const MlpLayout L{U, H};
+  const int NP = L.n_params();
+  const int total = a.n_reg * a.epochs;
+  // the helper's shared words live in the dpred area (unused by the loss pass)
+  int& s_q = ((int*)S.dpred())[0];
+  int& s_state = ((int*)S.dpred())[1];
+  int& s_best = ((int*)S.dpred())[2];
+  const Lanes ln(Smem<U, H>::SW0, Smem<U, H>::SW);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_q = __hip_atomic_fetch_add(a.lqueue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int q = s_q;
+    if (q >= total) break;
+    const int e = q / a.n_reg, job = q % a.n_reg;           // earlier epochs first
+    if (threadIdx.x == 0) {
+      const int32_t* rdy = a.ready + (int64_t)job * a.epochs + e;
+      int polls = 0, v = __hip_atomic_load(rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (v >= 0 && v < a.G && polls < kTeamSpinLimit) {
+        __builtin_amdgcn_s_sleep(2);
+        ++polls;
+        v = __hip_atomic_load(rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_state = v >= a.G ? 1 : v == kReadySkip ? 2 : 0;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int state = s_state;
+    float loss = state == 2 ? 0.0f : NAN;
+    if (state == 1) {
+      const float* rec = a.model + (int64_t)job * L.record();
+      for (int f = opaque_tid(); f < kMlpDin; f += kMlpThreads) {
+        S.xmean()[f] = rec[L.xmean_off() + f];
+        S.xinv()[f] = rec[L.xinv_off() + f];
+      }
+      if (opaque_tid() == 0) {
+        S.scal()[4] = rec[L.yscale_off()];
+        *S.wbase() = a.Wt;
+      }
+      load_weights<U, H>(S, a.snaps + ((int64_t)job * a.epochs + e) * NP, L);
+      __syncthreads();
+      const Feeder feed(a, a.dates[job]);
+      Team solo{nullptr, 1, 0, 0, false};
+      loss = full_loss<U, H>(S, ln, feed, a, solo, 0);
+    }
+    if (threadIdx.x == 0) {
+      a.losses[(int64_t)job * a.epochs + e] = loss;
+      if (a.loss_hist) a.loss_hist[(int64_t)job * a.epochs + e] = loss;
+      const int old = __hip_atomic_fetch_add(a.done + job, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      int best = -1;
+      if (old == a.epochs - 1) {                             // the date's last loss: keep the best epoch
+        float bl = INFINITY;
+        for (int k = 0; k < a.epochs; ++k) {
+          const float lk = a.losses[(int64_t)job * a.epochs + k];
+          if (lk < bl) {
+            bl = lk;
+            best = k;
+          }
+        }
+        if (a.model[(int64_t)job * L.record() + L.trained_off()] == 0.0f) best = -1;
+      }
+      s_best = best;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int best = s_best;
+    if (best >= 0) {
+      const float* src = a.snaps + ((int64_t)job * a.epochs + best) * NP;
+      float* rec = a.model + (int64_t)job * L.record();
+      for (int p = opaque_tid(); p < NP; p += kMlpThreads) rec[p] = src[p];
+    }
+  }
+}
+
 template <int U, int H>
 __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& tm, int team) {
   constexpr int R = kMlpRows;
@@ -1159,6 +1274,7 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
         for (int e = opaque_tid(); e < a.epochs; e += kMlpThreads) a.loss_hist[(int64_t)job * a.epochs + e] = 0.0f;
     }
     tm.sync();
+    if (a.snaps && tm.member == 0 && threadIdx.x == 0) mark_epochs(a, job, 0, kReadySkip);
     return;
   }
   load_weights<U, H>(S, P, L);
@@ -1220,6 +1336,14 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
       refit<U, H>(S, ln, feed, a, L, P, tm, team);
       pos = 1;
     }
+    if (a.snaps) {                       // the loss helpers take the loss and the best tracking
+      if (tm.failed) {
+        if (threadIdx.x == 0) mark_epochs(a, job, epoch - 1, kReadyFail);
+        return;
+      }
+      publish_snapshot(a, job, epoch, P, NP, tm);
+      continue;
+    }
     float loss = full_loss<U, H>(S, ln, feed, a, tm, team);
     if (tm.failed) loss = NAN;
     if (a.loss_hist && (tm.member == 0 || tm.failed) && opaque_tid() == 0)
@@ -1244,10 +1368,13 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_train_kernel(const MlpArgs a)
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   Smem<U, H> S{(__bf16*)smem_raw};
   const int b = blockIdx.x;
+  const int tgrid = 8 * a.G * ((a.n_teams + 7) / 8);
   const int team = b % 8 + 8 * ((b / 8) / a.G), member = (b / 8) % a.G;
-  if (team >= a.n_teams) return;
-  Team tm{a.team_ctr + team, a.G, member, 0, false};
-  for (int job = team; job < a.n_reg && !tm.failed; job += a.n_teams) train_one<U, H>(S, a, job, tm, team);
+  if (b < tgrid && team < a.n_teams) {
+    Team tm{a.team_ctr + team, a.G, member, 0, false};
+    for (int job = team; job < a.n_reg && !tm.failed; job += a.n_teams) train_one<U, H>(S, a, job, tm, team);
+  }
+  if (a.snaps) loss_helper<U, H>(S, a);
 }
 
 // Prediction with the best parameters: out[job][k] = ((f)^+ + mu) * y_scale (0 if untrained).
@@ -1295,6 +1422,7 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs 
     __syncthreads();
     const int t = opaque_tid();
     if (t < n) out[(int64_t)job * a.M + r0 + t] = (fmaxf(output_of_row<U, H>(S, t), 0.0f) + S.scal()[1]) * ysc;
+    if constexpr (H == 1) __syncthreads();   // the output partials are read before the next chunk writes them
     parity ^= 1;
   }
 }
@@ -1339,7 +1467,14 @@ hipError_t launch_mlp_train(const MlpArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, a.team_ctr, a.n_teams);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const unsigned grid = 8u * (unsigned)a.G * (unsigned)((a.n_teams + 7) / 8);
+  if (a.snaps) {
+    hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, a.ready, a.n_reg * a.epochs);
+    hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, a.done, a.n_reg);
+    hipLaunchKernelGGL(zero_i32, dim3(1), dim3(256), 0, s, a.lqueue, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const unsigned tgrid = 8u * (unsigned)a.G * (unsigned)((a.n_teams + 7) / 8);
+  const unsigned grid = a.snaps ? (unsigned)a.n_blocks : tgrid;
   void* args[] = {(void*)&a};
 #define X(u, h)                                                                                  \
   if (a.U == u && a.H == h) {                                                                    \

@@ -58,6 +58,16 @@ struct MlpArgs {
   int32_t G;                      // workgroups per team (one team trains one date at a time)
   int32_t n_teams;
   int32_t use_init;               // 1: start from `model` (warm start), 0: from the Philox draw
+  // Loss helpers (all dates trained at once): the full-sample loss of every epoch is computed by
+  // workgroups without a team (and by teams once they are done) from per-epoch parameter
+  // snapshots; the best epoch is chosen when a date's last loss is in.  snaps null: the teams
+  // compute the loss themselves.
+  float* snaps;                   // [n_reg][epochs][n_params]
+  int32_t* ready;                 // [n_reg][epochs] members' snapshot arrivals, or a marker < 0
+  int32_t* done;                  // [n_reg] losses computed
+  int32_t* lqueue;                // helper work counter
+  float* losses;                  // [n_reg][epochs]
+  int32_t n_blocks;               // workgroups of the launch (trainers first)
   int32_t dates[kMaxRegDates];
 };
 

@@ -73,20 +73,33 @@ bool choose_team(const cva_mlp_cfg* c, int n_dates, int& G, int& n_teams) {
   return true;
 }
 
+// Loss helpers run when every date has its team in the one launch and the device holds more
+// workgroups than the teams use (batched mode only).
+bool use_loss_helpers(const cva_mlp_cfg* c, int n_reg, int G, int n_teams) {
+  if (c->warm_start || n_teams != n_reg) return false;
+  const int capacity = mlp_max_teams(c->width, c->hidden, 1);
+  return capacity > G * n_teams;
+}
+
 struct RegWs {
-  size_t params, partial, gram, loss, ctr, total;
+  size_t params, partial, gram, loss, ctr, snaps, flags, losses, total;
 };
 
 RegWs reg_ws(const cva_mlp_cfg* c, int n_reg, int G, int n_teams) {
   const MlpLayout L{c->width, c->hidden};
   const size_t np = (size_t)L.n_params();
+  const bool helpers = use_loss_helpers(c, n_reg, G, n_teams);
+  const size_t ne = (size_t)n_reg * c->epochs;
   RegWs w;
   w.params = align256(3 * np * n_reg * sizeof(float));
   w.partial = align256(G > 1 ? np * G * n_teams * sizeof(float) : 0);
   w.gram = align256((size_t)(c->width + 1) * (c->width + 2) * G * n_teams * sizeof(double));
   w.loss = align256((size_t)G * n_teams * sizeof(double));
   w.ctr = align256((size_t)n_teams * sizeof(int32_t));
-  w.total = w.params + w.partial + w.gram + w.loss + w.ctr;
+  w.snaps = helpers ? align256(ne * np * sizeof(float)) : 0;
+  w.flags = helpers ? align256((ne + n_reg + 1) * sizeof(int32_t)) : 0;    // ready, done, queue
+  w.losses = helpers ? align256(ne * sizeof(float)) : 0;
+  w.total = w.params + w.partial + w.gram + w.loss + w.ctr + w.snaps + w.flags + w.losses;
   return w;
 }
 
@@ -138,8 +151,21 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
   a.loss_part = (double*)w;
   w += ws.loss;
   a.team_ctr = (int32_t*)w;
+  w += ws.ctr;
   a.G = G;
   a.n_teams = n_teams;
+  a.snaps = nullptr;
+  a.n_blocks = 0;
+  if (ws.snaps) {
+    a.snaps = (float*)w;
+    w += ws.snaps;
+    a.ready = (int32_t*)w;
+    a.done = a.ready + (size_t)n_reg * c->epochs;
+    a.lqueue = a.done + n_reg;
+    w += ws.flags;
+    a.losses = (float*)w;
+    a.n_blocks = mlp_max_teams(c->width, c->hidden, 1);
+  }
   a.X = X_dev;
   a.Y = Y_dev;
   a.Wt = W_dev;

@@ -24,7 +24,7 @@ def test_regression_team_is_cached(lib, tmp_path, monkeypatch):
     assert team in (1, 2, 4)
     cache = json.load(open(tmp_path / "tuned.json"))
     (key, entry), = cache.items()
-    assert entry["team"] == team and set(entry["epoch_ms"]) <= {"1", "2", "4"}
+    assert entry["team"] == team and set(entry["fit_ms"]) <= {"1", "2", "4"}
     # cached: the same answer without timing (candidates that could not run are not tried)
     assert autotune.regression_team(cfg, [1, 2, 3], X, Y, candidates=()) == team
     # and the tuned size trains like any other
