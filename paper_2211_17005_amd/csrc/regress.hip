@@ -181,9 +181,9 @@ struct Smem {
   static constexpr int SW0 = D + 16;           // padded row strides (bf16 elements)
   static constexpr int SW = U + 16;
   static constexpr int w_bytes = (U * SW0 + (H - 1) * U * SW) * (int)sizeof(__bf16);
-  static constexpr int a_bytes = (R * SW0 + H * R * SW) * (int)sizeof(__bf16);
+  static constexpr int a_bytes = (2 * R * SW0 + H * R * SW) * (int)sizeof(__bf16);
   static constexpr int f_count = 2 * H * U + 2 * U + 5 * R + 2 * D + 8;
-  static constexpr int red_bytes = kMlpThreads * 16;
+  static constexpr int red_bytes = kMlpThreads * 8;
   static constexpr int bytes = w_bytes + a_bytes + f_count * 4 + red_bytes;
   static_assert(bytes <= 160 * 1024, "LDS of one workgroup");
   static_assert(w_bytes % 16 == 0 && a_bytes % 16 == 0 && (f_count * 4) % 16 == 0, "16-byte sections");
@@ -194,8 +194,11 @@ struct Smem {
   }
   __device__ __bf16* A(int l) const {          // l = 0..H : [R][K + 8]
     __bf16* a0 = base + w_bytes / (int)sizeof(__bf16);
-    return l == 0 ? a0 : a0 + R * SW0 + (l - 1) * R * SW;
+    return l == 0 ? a0 : a0 + 2 * R * SW0 + (l - 1) * R * SW;
   }
+  // the second input buffer: a training chunk's successor is staged while it is back-propagated
+  __device__ __bf16* A0b() const { return base + w_bytes / (int)sizeof(__bf16) + R * SW0; }
+  __device__ __bf16* in_buf(int parity) const { return parity ? A0b() : A(0); }
   __device__ float* F() const { return (float*)((char*)base + w_bytes + a_bytes); }
   __device__ float* bias(int l) const { return F() + (l - 1) * U; }
   __device__ float* gbias(int l) const { return F() + H * U + (l - 1) * U; }
@@ -452,11 +455,11 @@ struct Masks {
 };
 
 template <int U, int H>
-__device__ Masks forward(const Smem<U, H>& S, const Lanes& ln) {
+__device__ Masks forward(const Smem<U, H>& S, const Lanes& ln, const __bf16* a0) {
   Masks k{{0u, 0u}};
-  k.m[0] = forward_layer<U, H, 1>(S, ln, S.A(0));
-  if constexpr (H >= 2) k.m[1] = forward_layer<U, H, 2>(S, ln, S.A(0));
-  if constexpr (H >= 3) forward_layer<U, H, 3>(S, ln, S.A(0));
+  k.m[0] = forward_layer<U, H, 1>(S, ln, a0);
+  if constexpr (H >= 2) k.m[1] = forward_layer<U, H, 2>(S, ln, a0);
+  if constexpr (H >= 3) forward_layer<U, H, 3>(S, ln, a0);
   return k;
 }
 
@@ -488,13 +491,13 @@ constexpr int dz_buf(int l, int H) { return l >= H - 1 ? l : l + 2; }
 // dW_L += dZ_L^T A_{L-1} over the chunk for the tiles this wave owns, and the bias gradient of
 // its out tiles (dZ_L^T times a ones column, in the waves owning in block 0).
 template <int U, int H, int L>
-__device__ void accumulate_dw(const Smem<U, H>& S, const Lanes& ln, f32x4* accW) {
+__device__ void accumulate_dw(const Smem<U, H>& S, const Lanes& ln, f32x4* accW, const __bf16* a0) {
   using M = DwMap<U, L>;
   const int wave = wave_id(), lane = lane_id();
   const int ib = wave % M::NIB, ob = wave / M::NIB;
   if (ob >= M::NOB) return;
   const __bf16* dZ = S.A(dz_buf(L, H));
-  const __bf16* Ain = S.A(L - 1);
+  const __bf16* Ain = L == 1 ? a0 : S.A(L - 1);
   constexpr int SW = Smem<U, H>::SW, SWin = Smem<U, H>::lds(L);
   const LaneOffsets& oz = ln.o;
   const LaneOffsets& oi = L == 1 ? ln.o0 : ln.o;
@@ -581,15 +584,16 @@ __device__ void backprop_store(const Smem<U, H>& S, const Lanes& ln, const f32x4
 }
 
 template <int U, int H, int L>
-__device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW) {
-  accumulate_dw<U, H, L>(S, ln, accW);
+__device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW,
+                               const __bf16* a0) {
+  accumulate_dw<U, H, L>(S, ln, accW, a0);
   if constexpr (L > 1) {
     f32x4 dh[Blk<U>::BO][Blk<U>::BR];
     backprop_compute<U, H, L>(S, ln, dh);
     if constexpr (dz_buf(L - 1, H) == L - 1) __syncthreads();   // in place: A(L-1) is read above
     backprop_store<U, H, L>(S, ln, dh, mk.m[L - 2]);
     __syncthreads();
-    layer_backward<U, H, L - 1>(S, ln, mk, accW);
+    layer_backward<U, H, L - 1>(S, ln, mk, accW, a0);
   } else {
     __syncthreads();
   }
@@ -597,7 +601,7 @@ __device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, const Masks
 
 // Gradients of one chunk, accumulated over the batch.  dff of the chunk's rows is in LDS.
 template <int U, int H>
-__device__ void backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW) {
+__device__ void backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW, const __bf16* a0) {
   const int tid = opaque_tid();
   // dZ_H = [A_H > 0] dff w_out^T in place, and the partial sums of dff^T A_H (output weights)
   {
@@ -620,18 +624,22 @@ __device__ void backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, 
       }
       *p = z;
     }
-    ((f32x4*)S.red())[rs * UQ + uq] = g;
+    // lanes of a wave that share uq first (the reduction area holds one partial per wave)
+#pragma unroll
+    for (int m = UQ; m < 64; m <<= 1)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[q] += __shfl_xor(g[q], m);
+    if (lane_id() < UQ) ((f32x4*)S.red())[wave_id() * UQ + uq] = g;
   }
   __syncthreads();
   if (tid < U) {
-    constexpr int RS = kMlpThreads / (U / 4);
     const float* part = (const float*)S.red();
     float s = S.gwout()[tid];
 #pragma unroll
-    for (int q = 0; q < RS; ++q) s += part[q * U + tid];
+    for (int w = 0; w < kMlpWaves; ++w) s += part[w * U + tid];
     S.gwout()[tid] = s;
   }
-  layer_backward<U, H, H>(S, ln, mk, accW);
+  layer_backward<U, H, H>(S, ln, mk, accW, a0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -924,7 +932,7 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
   // thread t, column u = t % U, row group t / U of the chunk: sum w h_u, sum w h_u (y - mu); the
   // threads of column 0 also sum w (y - mu) and w.  Groups are combined in a fixed order below.
   constexpr int NGRP = kMlpThreads / U;
-  static_assert(NGRP * U == kMlpThreads && 2 * kMlpThreads * 8 <= Smem<U, H>::red_bytes, "column groups");
+  static_assert(NGRP * U == kMlpThreads && kMlpThreads * 8 <= Smem<U, H>::red_bytes, "column groups");
   double hs = 0.0, hy = 0.0, ys = 0.0, sw = 0.0;
   const float mu = S.scal()[1];
   const int64_t stride = (int64_t)R * tm.G, first = (int64_t)R * tm.member;
@@ -934,7 +942,7 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
     store_chunk<U, H>(S, c, feed.weight(S.wbase(), r0, n), n);
     if (r0 + stride < a.M) c = feed.load(r0 + stride, (int)min((int64_t)R, a.M - r0 - stride));
     __syncthreads();
-    forward<U, H>(S, ln);
+    forward<U, H>(S, ln, S.A(0));
     __bf16* Hh = S.A(H);
     const LaneOffsets& oh = ln.o;
     if (n < R) {                              // rows beyond the sample take no part
@@ -991,17 +999,18 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
   }
   double* rhs = G + N * N;
   {
-    double* red = (double*)S.red();
+    double* red = (double*)S.red();         // one double per thread: the two sums in turn
     const int u = tid % U, grp = tid / U;
-    red[grp * 2 * U + u] = hs;
-    red[grp * 2 * U + U + u] = hy;
+    double a = 0.0, b = 0.0;
+    red[tid] = hs;
+    __syncthreads();
+    if (tid < U)
+      for (int g = 0; g < NGRP; ++g) a += red[g * U + tid];
+    __syncthreads();
+    red[tid] = hy;
     __syncthreads();
     if (tid < U) {
-      double a = 0.0, b = 0.0;
-      for (int g = 0; g < NGRP; ++g) {
-        a += red[g * 2 * U + tid];
-        b += red[g * 2 * U + U + tid];
-      }
+      for (int g = 0; g < NGRP; ++g) b += red[g * U + tid];
       G[tid * N + U] = a;
       G[U * N + tid] = a;
       rhs[tid] = b;
@@ -1301,18 +1310,23 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
 #pragma unroll
       for (int s = 0; s < dw_slots(U, H); ++s) accW[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
       const int64_t first = b0 + (int64_t)R * tm.member;
-      ChunkRegs c = feed.load(first, (int)max((int64_t)0, min((int64_t)R, b1 - first)));
+      auto rows = [&](int64_t r) { return (int)max((int64_t)0, min((int64_t)R, b1 - r)); };
+      // the batch's first chunk is staged here, every later one into the other input buffer while
+      // its predecessor is back-propagated (the last barrier of that pass publishes it)
+      ChunkRegs c = feed.load(first, rows(first));
+      if (first < b1) store_chunk<U, H>(S, c, feed.weight(S.wbase(), first, rows(first)), rows(first), S.in_buf(0));
+      if (first + cstride < b1) c = feed.load(first + cstride, rows(first + cstride));
+      __syncthreads();
+      int parity = 0;
       for (int64_t r0 = first; r0 < b1; r0 += cstride) {
-        const int n = (int)min((int64_t)R, b1 - r0);
-        const float y = store_chunk<U, H>(S, c, feed.weight(S.wbase(), r0, n), n).y;
-        if (r0 + cstride < b1) c = feed.load(r0 + cstride, (int)min((int64_t)R, b1 - r0 - cstride));
-        __syncthreads();
-        const Masks mk = forward<U, H>(S, ln);
+        const int n = rows(r0);
+        const __bf16* a0 = S.in_buf(parity);
+        const Masks mk = forward<U, H>(S, ln, a0);
         if (opaque_tid() < R) {             // wave 0: one row per lane
           const int r = opaque_tid();
           const float f = output_of_row<U, H>(S, r);
           const float pred = (pos ? fmaxf(f, 0.0f) : f) + S.scal()[1];
-          const float dp = r < n ? 2.0f * S.wbuf()[r] * (pred - y) * inv_batch : 0.0f;
+          const float dp = r < n ? 2.0f * S.wbuf()[r] * (pred - S.ybuf()[r]) * inv_batch : 0.0f;
           const float df = pos ? (f > 0.0f ? dp : 0.0f) : dp;
           S.dff()[r] = df;
           const float gm = wave_sum(dp), gb = wave_sum(df);
@@ -1322,7 +1336,13 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
           }
         }
         __syncthreads();
-        backward<U, H>(S, ln, mk, accW);
+        if (r0 + cstride < b1) {
+          const int nn = rows(r0 + cstride);
+          store_chunk<U, H>(S, c, feed.weight(S.wbase(), r0 + cstride, nn), nn, S.in_buf(parity ^ 1));
+          if (r0 + 2 * cstride < b1) c = feed.load(r0 + 2 * cstride, rows(r0 + 2 * cstride));
+        }
+        backward<U, H>(S, ln, mk, accW, a0);
+        parity ^= 1;
       }
       p1 *= a.beta1;
       p2 *= a.beta2;
