@@ -11,7 +11,8 @@ Readings taken where the listing is garbled or silent:
   * one simultaneous backpropagation step updates all layers and mu per batch;
   * pos = 0 until epoch floor(E/2); at the end of that epoch the output layer
     (W^{h+1}, b^{h+1}) is refitted in closed form by least squares on the full
-    sample with the hidden layers frozen and mu fixed (pos = 0 loss); then pos = 1;
+    sample with the hidden layers frozen and mu fixed (pos = 0 loss; the minimum-norm
+    solution where the hidden features are rank deficient); then pos = 1;
   * after every epoch the full-sample pos = 1 loss is evaluated and the best
     parameters are kept (the comparison uses pos = 1 in both halves);
   * the prediction uses the best parameters and the output ReLU: (f)^+ + mu;
@@ -24,7 +25,7 @@ Readings taken where the listing is garbled or silent:
     whose targets are all 0 is not trained and predicts 0.
 
 Row weights (optional, w >= 0): every loss becomes (1/|rows|) sum w (pred - y)^2 and the
-refit solves the weighted normal equations.  With the grouped form of the per-inner-sample
+refit solves the weighted least-squares problem.  With the grouped form of the per-inner-sample
 regression (``inner.alive_targets``), the weighted loss over outer paths equals the paper's
 loss over all (path, draw) samples of the group up to a constant; integer weights equal
 duplicated rows.  The scaling statistics stay unweighted (they only fix units).
@@ -173,22 +174,24 @@ class Adam:
         net.mu -= self.lr * mh / (np.sqrt(vh) + self.eps)
 
 
-REFIT_RIDGE = 1e-4
-
-
 def refit_output_layer(net: Net, X, y, w=None) -> None:
     """Closed-form least squares for (W^{h+1}, b^{h+1}) with frozen hidden layers, mu fixed.
 
-    Solved from the normal equations of [H, 1] with a ridge of REFIT_RIDGE times the mean
-    diagonal of the Gram matrix (reading: the hidden features are often nearly collinear and
-    dead ReLU units give zero columns; the ridge makes the closed form well posed).
+    Algorithm 1 (Section 2.2) refits the output layer in closed form on the whole sample: the
+    argmin over (W^{h+1}, b^{h+1}) of the pos = 0 loss (1/M) sum w (H W + b + mu - y)^2, where H
+    are the last hidden layer's activations.  The fitted values of a least-squares problem are
+    unique; where [H, 1] is rank deficient (a dead ReLU unit is an all-zero column) the weights
+    are not, and the minimum-norm solution is taken (numpy's SVD least squares), which gives a
+    zero column weight 0.  Weighted rows scale both sides by sqrt(w).
     """
     acts, _, _ = forward(net, X)
     H = np.concatenate([acts[-1], np.ones((X.shape[0], 1))], axis=1)
-    Hw = H if w is None else H * w[:, None]
-    G = Hw.T @ H
-    lam = REFIT_RIDGE * np.trace(G) / G.shape[0]
-    sol = np.linalg.solve(G + lam * np.eye(G.shape[0]), Hw.T @ (y - net.mu))
+    r = y - net.mu
+    if w is not None:
+        s = np.sqrt(w)
+        H = H * s[:, None]
+        r = r * s
+    sol, *_ = np.linalg.lstsq(H, r, rcond=None)
     net.W[-1] = sol[:-1][None, :].copy()
     net.b[-1] = np.array([sol[-1]])
 

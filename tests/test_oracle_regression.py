@@ -67,31 +67,122 @@ def test_first_adam_step_moves_by_signed_lr():
     assert np.isclose(net.mu - before.mu, -1e-2 * gmu / (abs(gmu) + 1e-8), rtol=1e-12)
 
 
-def test_output_refit_is_stationary():
-    """After the closed-form refit, the gradient of the ridge-penalised pos=0 loss in
-    (W^{h+1}, b^{h+1}) vanishes, and with the ridge switched off the refit is the OLS fit."""
+def _hidden(net, X):
+    acts, _, _ = rg.forward(net, X)
+    return np.concatenate([acts[-1], np.ones((X.shape[0], 1))], axis=1)
+
+
+def test_output_refit_solves_the_least_squares_problem():
+    """Algorithm 1's closed-form refit is the argmin of the pos = 0 loss over the output layer:
+    at the solution the loss gradient in (W^{h+1}, b^{h+1}) vanishes (normal equations), and no
+    perturbation of the output layer lowers the loss."""
     X, y = rand_problem(M=200)
     net = rg.init_net(3, 2, 6, seed=5)
     net.mu = 0.3
     rg.refit_output_layer(net, X, y)
     gW, gb, _ = rg.grads(net, X, y, 0)
-    acts, _, _ = rg.forward(net, X)
-    H = np.concatenate([acts[-1], np.ones((X.shape[0], 1))], axis=1)
+    H = _hidden(net, X)
+    scale = np.abs(H).max() * np.abs(y - net.mu).max()
+    assert np.max(np.abs(gW[-1][0])) < 1e-12 * scale
+    assert abs(gb[-1][0]) < 1e-12 * scale
+    L0 = rg.loss(net, X, y, 0)
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        p = net.copy()
+        p.W[-1] = p.W[-1] + 1e-3 * rng.standard_normal(p.W[-1].shape)
+        p.b[-1] = p.b[-1] + 1e-3 * rng.standard_normal(1)
+        assert rg.loss(p, X, y, 0) >= L0
+
+
+def test_output_refit_recovers_an_exact_linear_target():
+    """Targets exactly affine in the hidden features: the refit returns those coefficients."""
+    X, _ = rand_problem(M=300, seed=4)
+    net = rg.init_net(3, 2, 6, seed=8)
+    net.b = [np.linspace(0.2, 0.6, v.size) for v in net.b]      # every unit active somewhere
+    net.mu = -0.1
+    H = _hidden(net, X)
+    assert np.linalg.matrix_rank(H) == H.shape[1]
+    w_true = np.array([0.5, -1.25, 2.0, 0.0, 0.75, -0.3, 0.05])
+    y = H @ w_true + net.mu
+    rg.refit_output_layer(net, X, y)
+    got = np.concatenate([net.W[-1][0], net.b[-1]])
+    assert np.allclose(got, w_true, rtol=0, atol=1e-10)
+
+
+def test_output_refit_minimum_norm_on_dead_and_duplicated_units():
+    """Rank-deficient hidden features: a dead ReLU unit (all-zero column) gets weight 0 and two
+    identical units share their weight equally (the minimum-norm least-squares solution), while
+    the fitted values stay those of the full-rank problem without the redundant columns."""
+    X, y = rand_problem(M=250, seed=6)
+    net = rg.init_net(3, 2, 6, seed=9)
+    net.b[1][2] = -1e3                       # unit 2 of the last hidden layer never fires
+    net.W[1][4] = net.W[1][1]                # unit 4 duplicates unit 1
+    net.b[1][4] = net.b[1][1]
+    net.mu = 0.1
+    rg.refit_output_layer(net, X, y)
+    w = net.W[-1][0]
+    H = _hidden(net, X)
+    assert np.all(H[:, 2] == 0.0)
+    assert abs(w[2]) < 1e-12
+    assert abs(w[4] - w[1]) < 1e-10 * max(1.0, abs(w[1]))
+    keep = [0, 1, 3, 5, 6]                   # independent columns (bias last)
+    Hk = H[:, keep]
+    coef = np.linalg.solve(Hk.T @ Hk, Hk.T @ (y - net.mu))
+    assert np.allclose(H @ np.concatenate([w, net.b[-1]]), Hk @ coef, rtol=0, atol=1e-10)
+
+
+def _guarded_cholesky_fit(H, r, guard=1e-12):
+    """The library's refit solve written out in NumPy: normal equations of [H, 1], a Cholesky
+    factorisation in which a column whose diagonal is zero, or whose pivot falls to
+    guard x its diagonal, is dropped (weight 0); the rest solved by the two triangular solves."""
     G = H.T @ H
-    lam = rg.REFIT_RIDGE * np.trace(G) / G.shape[0]
-    # d/dw [ (1/M) |H w + mu - y|^2 + (lam/M) |w|^2 ] = grads + 2 lam w / M
-    w = np.concatenate([net.W[-1][0], net.b[-1]])
-    pen = 2.0 * lam * w / X.shape[0]
-    assert np.max(np.abs(gW[-1][0] + pen[:-1])) < 1e-10
-    assert abs(gb[-1][0] + pen[-1]) < 1e-10
-    old = rg.REFIT_RIDGE
-    try:
-        rg.REFIT_RIDGE = 0.0
-        rg.refit_output_layer(net, X, y)
-    finally:
-        rg.REFIT_RIDGE = old
-    sol, *_ = np.linalg.lstsq(H, y - net.mu, rcond=None)
-    assert np.allclose(np.concatenate([net.W[-1][0], net.b[-1]]), sol, rtol=1e-8, atol=1e-10)
+    rhs = H.T @ r
+    n = G.shape[0]
+    Lm = G.copy()
+    drop = np.zeros(n, dtype=bool)
+    for k in range(n):
+        p = Lm[k, k]
+        if G[k, k] == 0.0 or p <= guard * G[k, k]:
+            drop[k] = True
+            Lm[k:, k] = 0.0
+            Lm[k, k] = 1.0
+            continue
+        Lm[k, k] = np.sqrt(p)
+        Lm[k + 1:, k] /= Lm[k, k]
+        Lm[k + 1:, k + 1:] -= np.outer(Lm[k + 1:, k], Lm[k + 1:, k])
+    L = np.tril(Lm)
+    z = np.zeros(n)
+    for i in range(n):
+        z[i] = 0.0 if drop[i] else (rhs[i] - L[i, :i] @ z[:i]) / L[i, i]
+    x = np.zeros(n)
+    for i in range(n - 1, -1, -1):
+        x[i] = 0.0 if drop[i] else (z[i] - L[i + 1:, i] @ x[i + 1:]) / L[i, i]
+    return x, drop
+
+
+def test_library_refit_rule_gives_the_least_squares_fitted_values():
+    """The GPU solves the refit by a Cholesky factorisation of the normal equations that drops
+    zero and dependent columns (pivot <= 1e-12 x diagonal).  On the hidden features of a
+    three-layer, 128-unit network with dead units and nearly collinear columns, its fitted
+    values equal the oracle's minimum-norm least squares to 1e-9 relative."""
+    rng = np.random.default_rng(11)
+    M, d = 4096, 29
+    X = rng.standard_normal((M, d))
+    y = np.log1p(np.exp(X @ rng.standard_normal(d) / np.sqrt(d))) + 0.1 * rng.standard_normal(M)
+    net = rg.init_net(d, 3, 128, seed=2)
+    net.b[2][:10] = -50.0                     # ten dead units in the last hidden layer
+    net.W[2][20] = net.W[2][21] * (1 + 1e-13)  # an (almost) exactly duplicated unit
+    net.b[2][20] = net.b[2][21] * (1 + 1e-13)
+    H = _hidden(net, X)
+    r = y - 0.05
+    ref = net.copy()
+    ref.mu = 0.05
+    rg.refit_output_layer(ref, X, y)
+    f_ref = H @ np.concatenate([ref.W[-1][0], ref.b[-1]])
+    x, drop = _guarded_cholesky_fit(H, r)
+    assert drop[:10].all() and drop.sum() >= 11
+    f = H @ x
+    assert np.linalg.norm(f - f_ref) <= 1e-9 * np.linalg.norm(f_ref)
 
 
 def test_linear_network_converges_to_ols():
