@@ -54,7 +54,8 @@ enum hsim_status {
   HSIM_ERANGE = -2,       /* a size beyond the supported limits */
   HSIM_ENOWS = -3,        /* workspace too small */
   HSIM_EDEVICE = -4,      /* a HIP runtime call failed */
-  HSIM_EUNSUPPORTED = -5  /* a shape the library was not built for */
+  HSIM_EUNSUPPORTED = -5, /* a shape the library was not built for */
+  HSIM_ETIMEOUT = -6      /* a bounded device-side wait gave up; the results are incomplete */
 };
 
 /* Arithmetic of the simulation.  HSIM_FP64: all state and prices in FP64.  HSIM_FP32:
@@ -293,9 +294,13 @@ size_t hsim_workspace_bytes(int op, const hsim_market* market, const hsim_grid* 
  * Network: `hidden` ReLU layers of `width` units and a linear output f; prediction
  * (f)^+ + mu.  Training of one date (BaseAlg with Adam): `epochs` epochs of contiguous
  * batches of `batch` rows; pos = 0 (no output ReLU) until epoch floor(epochs/2), at the end of
- * which the output layer is refitted by least squares on the full sample with the hidden layers
- * frozen and mu fixed, then pos = 1; after every epoch the full-sample pos = 1 loss is computed
- * and the best parameters are kept.  Inputs are standardised per date (population mean and
+ * which the output layer is refitted in closed form with the hidden layers frozen and mu fixed
+ * (the least-squares argmin of the pos = 0 loss: normal equations of [H 1] accumulated in FP64,
+ * solved by a Cholesky factorisation in which a column with a zero diagonal or a pivot at or
+ * below 1e-12 times its diagonal is linearly dependent on the columns before it and gets weight
+ * 0, which leaves the fitted values those of the full least-squares problem), then pos = 1;
+ * after every epoch the full-sample pos = 1 loss is computed and the best parameters are kept
+ * (E = 1 therefore takes no refit).  Inputs are standardised per date (population mean and
  * standard deviation over the M rows) and targets divided by their root mean square; a date
  * whose targets are all zero is not trained and predicts 0.  Initial weights are
  * U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from Philox words (layer, idx >> 2, init_tag, 2) with the
@@ -309,7 +314,7 @@ typedef struct {
   int32_t d_in;       /* inputs per row, 1..32 (the first d_in features of X) */
   int32_t epochs;     /* E >= 1 */
   int32_t batch;      /* rows per SGD batch; the last batch of an epoch may be shorter */
-  float lr, beta1, beta2, eps;  /* Adam */
+  float lr, beta1, beta2, eps;  /* Adam (lr >= 0; lr = 0 leaves the network as initialised) */
   int32_t warm_start; /* 0: every date trains independently from the same initial draw, all dates
                          in one persistent launch; 1: Backward learning, dates trained one after
                          another in the order given, each started from the previous date's result */
@@ -321,6 +326,12 @@ typedef struct {
 
 /* Floats per date of the model array written by cva_regress_fit (parameters, then scaling). */
 int cva_regress_record_floats(const cva_mlp_cfg* cfg);
+
+/* Floats of the parameters at the head of a model record, in the order
+ * W_1 [width][32] (columns >= d_in zero), b_1, W_2 [width][width], b_2, ..., W_hidden, b_hidden,
+ * w_out [width], b_out, mu; the record continues with the input means [32], the inverse standard
+ * deviations [32], the target scale and a trained flag. */
+int cva_regress_param_floats(const cva_mlp_cfg* cfg);
 
 /* Device workspace for cva_regress_fit. */
 size_t cva_regress_workspace_bytes(const cva_mlp_cfg* cfg, int32_t n_reg, int64_t M);
@@ -334,11 +345,25 @@ size_t cva_regress_workspace_bytes(const cva_mlp_cfg* cfg, int32_t n_reg, int64_
  *   per-inner-sample regression, Section 3.2),
  * date index dates[j] (host array).  model_dev [n_reg][cva_regress_record_floats] receives
  * the best parameters and the input scaling; loss_hist_dev [n_reg][epochs] (may be NULL) the
- * full-sample loss after every epoch (in units of the scaled targets).  n_reg <= 512. */
+ * full-sample loss after every epoch (in units of the scaled targets).  n_reg <= 512.
+ * The team barriers and the loss helpers' waits are bounded: should one give up (it cannot while
+ * every workgroup of the cooperative launch is resident), the fit stops early and the call
+ * returns HSIM_ETIMEOUT.  Synchronous: returns once the fit on `stream` has completed. */
 int cva_regress_fit(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,
                     int64_t M, int32_t n_feat, const float* X_dev, const float* Y_dev,
                     const float* W_dev, uint64_t seed, float* model_dev, float* loss_hist_dev,
                     void* workspace_dev, size_t ws_bytes, void* stream);
+
+/* Test hook: after a cva_regress_fit call with the same cfg, n_reg and M on this workspace, copy
+ * each date's last parameters and Adam moments (FP32, [n_reg][n_params] each, the parameter order
+ * of the model record; any output may be NULL).  With epochs = 1 and batch = M they hold one
+ * Adam step: m = (1 - beta1) g and v = (1 - beta2) g^2 of the full-sample gradient g. */
+int cva_regress_adam_state(const cva_mlp_cfg* cfg, int32_t n_reg, int64_t M, const void* workspace_dev,
+                           size_t ws_bytes, float* params_dev, float* m_dev, float* v_dev, void* stream);
+
+/* Test hook: the number of polls after which the regression's bounded waits give up (0 restores
+ * the default, 2^22 polls of about a microsecond each).  Process-wide; affects later fits. */
+int hsim_set_wait_limit(int32_t polls);
 
 /* Predictions out_dev [n_reg][M] = ((f)^+ + mu) * y_scale of the fitted networks on X_dev. */
 int cva_regress_predict(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,

@@ -645,19 +645,20 @@ __device__ void backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, 
 // ------------------------------------------------------------------------------------------
 // teams: G workgroups training one date together
 // ------------------------------------------------------------------------------------------
-constexpr int kTeamSpinLimit = 1 << 22;   // polls before a team barrier gives up (several seconds)
-
 // Barrier of the G workgroups of a team: a monotonic arrival counter in global memory.  Every
 // wave waits for its global stores to complete, the workgroup's arrival (an agent-scope release)
 // publishes them; the arriving thread polls the counter without ordering, acquires once when it
 // is reached, and after the barrier every wave invalidates its stale cached lines.  All workgroups of a launch are resident
 // (cooperative launch), so the wait ends; should it not within the poll limit, the workgroup
-// marks itself failed, stops waiting at later barriers (it still arrives) and leaves the fit at
-// the end of the epoch with a NaN loss, so a launch always terminates.
+// marks itself failed, records the give-up in the launch's status word, stops waiting at later
+// barriers (it still arrives) and leaves the fit at the end of the epoch with a NaN loss, so a
+// launch always terminates and the host learns of it.
 struct Team {
   int32_t* ctr;
   int G, member, arrivals;
   bool failed;
+  int32_t* status;
+  int spin_limit;
   __device__ void sync() {
     if (G == 1) {
       __syncthreads();
@@ -673,16 +674,17 @@ struct Team {
     if (threadIdx.x == 0) {
       __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       const int target = arrivals * G;
-      int polls = failed ? kTeamSpinLimit : 0;
+      int polls = failed ? spin_limit : 0;
       // relaxed polls (an acquiring poll would invalidate the cache on every iteration), one
       // acquire fence once the count is reached
-      while (polls < kTeamSpinLimit &&
+      while (polls < spin_limit &&
              __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(2);
         ++polls;
       }
-      s_failed = polls == kTeamSpinLimit &&
+      s_failed = polls >= spin_limit &&
                  __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target;
+      if (s_failed && status) __hip_atomic_fetch_or(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
@@ -1045,49 +1047,54 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
   }
   __threadfence_block();
   __syncthreads();
-  // ridge of kRefitRidge times the mean diagonal: keeps dead units (zero columns) at weight 0 and
-  // bounds the conditioning of the normal equations
-  if (tid == 0) {
-    double tr = 0.0;
-#pragma unroll 1
-    for (int i = 0; i < N; ++i) tr += G[i * N + i];
-    const double lam = kRefitRidge * tr / N + 1e-300;
-#pragma unroll 1
-    for (int i = 0; i < N; ++i) G[i * N + i] += lam;
-  }
+  // Algorithm 1's refit is the plain least-squares argmin.  Its fitted values are unique; where
+  // [H 1] is rank deficient (a dead ReLU unit is an all-zero column, two units may coincide) the
+  // weights are not, and a column whose diagonal is zero, or whose Cholesky pivot falls to
+  // kRefitGuard times its diagonal (dependent on the columns before it to working precision),
+  // is dropped with weight 0: the fitted values are those of the full problem.  A dropped
+  // column is marked by a zero on the factor's diagonal; its entries below are zeroed so it
+  // takes no part in the trailing updates or the triangular solves.  The original diagonal of
+  // column k >= 1 is kept in the unused upper triangle at (k - 1, k).
+  for (int k = 1 + opaque_tid(); k < N; k += kMlpThreads) G[(k - 1) * N + k] = G[k * N + k];
   __threadfence_block();
   __syncthreads();
   // Cholesky (lower, in place), all threads on the trailing update
   for (int k = 0; k < N; ++k) {
-    if (opaque_tid() == 0) G[k * N + k] = sqrt(G[k * N + k]);
+    if (opaque_tid() == 0) {
+      const double d = k == 0 ? G[0] : G[(k - 1) * N + k];
+      const double p = G[k * N + k];
+      G[k * N + k] = (d > 0.0 && p > kRefitGuard * d) ? sqrt(p) : 0.0;
+    }
     __threadfence_block();
     __syncthreads();
     const double dkk = G[k * N + k];
-    for (int i = k + 1 + opaque_tid(); i < N; i += kMlpThreads) G[i * N + k] /= dkk;
+    for (int i = k + 1 + opaque_tid(); i < N; i += kMlpThreads) G[i * N + k] = dkk > 0.0 ? G[i * N + k] / dkk : 0.0;
     __threadfence_block();
     __syncthreads();
-    const int m = N - k - 1;
-    for (int e = opaque_tid(); e < m * m; e += kMlpThreads) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j <= i) G[i * N + j] -= G[i * N + k] * G[j * N + k];
+    if (dkk > 0.0) {
+      const int m = N - k - 1;
+      for (int e = opaque_tid(); e < m * m; e += kMlpThreads) {
+        const int i = k + 1 + e / m, j = k + 1 + e % m;
+        if (j <= i) G[i * N + j] -= G[i * N + k] * G[j * N + k];
+      }
     }
     __threadfence_block();
     __syncthreads();
   }
   if (opaque_tid() == 0) {
 #pragma unroll 1
-    for (int i = 0; i < N; ++i) {          // L y = rhs
+    for (int i = 0; i < N; ++i) {          // L y = rhs (dropped columns: 0)
       double s = rhs[i];
 #pragma unroll 1
       for (int j = 0; j < i; ++j) s -= G[i * N + j] * rhs[j];
-      rhs[i] = s / G[i * N + i];
+      rhs[i] = G[i * N + i] > 0.0 ? s / G[i * N + i] : 0.0;
     }
 #pragma unroll 1
     for (int i = N - 1; i >= 0; --i) {     // L^T x = y
       double s = rhs[i];
 #pragma unroll 1
       for (int j = i + 1; j < N; ++j) s -= G[j * N + i] * rhs[j];
-      rhs[i] = s / G[i * N + i];
+      rhs[i] = G[i * N + i] > 0.0 ? s / G[i * N + i] : 0.0;
     }
   }
   __threadfence_block();
@@ -1165,13 +1172,16 @@ __device__ void loss_helper(const Smem<U, H>& S, const MlpArgs& a) {
     if (threadIdx.x == 0) {
       const int32_t* rdy = a.ready + (int64_t)job * a.epochs + e;
       int polls = 0, v = __hip_atomic_load(rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      while (v >= 0 && v < a.G && polls < kTeamSpinLimit) {
+      while (v >= 0 && v < a.G && polls < a.spin_limit) {
         __builtin_amdgcn_s_sleep(2);
         ++polls;
         v = __hip_atomic_load(rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_state = v >= a.G ? 1 : v == kReadySkip ? 2 : 0;
+      // a snapshot that never came: the wait gave up (a failed team has recorded its own)
+      if (v >= 0 && v < a.G && a.status)
+        __hip_atomic_fetch_or(a.status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -1190,7 +1200,7 @@ __device__ void loss_helper(const Smem<U, H>& S, const MlpArgs& a) {
       load_weights<U, H>(S, a.snaps + ((int64_t)job * a.epochs + e) * NP, L);
       __syncthreads();
       const Feeder feed(a, a.dates[job]);
-      Team solo{nullptr, 1, 0, 0, false};
+      Team solo{nullptr, 1, 0, 0, false, nullptr, 0};
       loss = full_loss<U, H>(S, ln, feed, a, solo, 0);
     }
     if (threadIdx.x == 0) {
@@ -1391,7 +1401,7 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_train_kernel(const MlpArgs a)
   const int tgrid = 8 * a.G * ((a.n_teams + 7) / 8);
   const int team = b % 8 + 8 * ((b / 8) / a.G), member = (b / 8) % a.G;
   if (b < tgrid && team < a.n_teams) {
-    Team tm{a.team_ctr + team, a.G, member, 0, false};
+    Team tm{a.team_ctr + team, a.G, member, 0, false, a.status, a.spin_limit};
     for (int job = team; job < a.n_reg && !tm.failed; job += a.n_teams) train_one<U, H>(S, a, job, tm, team);
   }
   if (a.snaps) loss_helper<U, H>(S, a);

@@ -11,7 +11,8 @@ constexpr int kMlpWaves = kMlpThreads / 64;
 constexpr int kMlpRows = 64;         // rows of a chunk staged in LDS
 constexpr int kMlpDin = 32;          // input width, padded to one MFMA K step
 constexpr int kMaxRegDates = 512;
-constexpr double kRefitRidge = 1e-4;  // ridge of the output-layer refit, relative to the mean diagonal
+constexpr int kTeamSpinLimit = 1 << 22;  // default polls before a bounded wait gives up (several seconds)
+constexpr double kRefitGuard = 1e-12; // refit: a Cholesky pivot at or below this times its diagonal drops the column
 
 // Layout of one date's model record (floats):
 //   [ W_1 (U x 32) | b_1 (U) | W_2 (U x U) | b_2 | ... | W_H | b_H | w_out (U) | b_out | mu |
@@ -54,6 +55,8 @@ struct MlpArgs {
   double* gram;                   // [n_teams][G][(U+1)*(U+2)] refit normal equations
   double* loss_part;              // [n_teams][G] per-workgroup loss sums
   int32_t* team_ctr;              // [n_teams] barrier arrivals (zeroed before the launch)
+  int32_t* status;                // one word: nonzero when a bounded wait gave up (zeroed per fit)
+  int32_t spin_limit;             // polls before a bounded wait gives up
   float* loss_hist;               // [n_reg][epochs] or null
   int32_t G;                      // workgroups per team (one team trains one date at a time)
   int32_t n_teams;

@@ -1,6 +1,7 @@
 // C-ABI of the regression: cva_regress_fit / cva_regress_predict.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
 
 #include "../../include/hsim.h"
@@ -18,7 +19,7 @@ int check_cfg(const cva_mlp_cfg* c) {
   if (c->d_in < 1 || c->d_in > kMlpDin) return fail(HSIM_ERANGE, "d_in=%d out of [1,%d]", c->d_in, kMlpDin);
   if (c->epochs < 1 || c->batch < 1) return fail(HSIM_EINVAL, "epochs and batch must be >= 1");
   if (c->team < 0 || c->team > 32) return fail(HSIM_ERANGE, "team=%d out of [0,32]", c->team);
-  if (!(c->lr > 0.0f) || !(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f) ||
+  if (!(c->lr >= 0.0f) || !(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f) ||
       !(c->eps > 0.0f))
     return fail(HSIM_EINVAL, "bad Adam hyper-parameters");
   return HSIM_OK;
@@ -95,7 +96,7 @@ RegWs reg_ws(const cva_mlp_cfg* c, int n_reg, int G, int n_teams) {
   w.partial = align256(G > 1 ? np * G * n_teams * sizeof(float) : 0);
   w.gram = align256((size_t)(c->width + 1) * (c->width + 2) * G * n_teams * sizeof(double));
   w.loss = align256((size_t)G * n_teams * sizeof(double));
-  w.ctr = align256((size_t)n_teams * sizeof(int32_t));
+  w.ctr = align256((size_t)(n_teams + 1) * sizeof(int32_t));   // team counters, then the status word
   w.snaps = helpers ? align256(ne * np * sizeof(float)) : 0;
   w.flags = helpers ? align256((ne + n_reg + 1) * sizeof(int32_t)) : 0;    // ready, done, queue
   w.losses = helpers ? align256(ne * sizeof(float)) : 0;
@@ -107,9 +108,60 @@ __global__ void copy_params(const float* src, float* dst, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
+__global__ void zero_word(int32_t* p) { *p = 0; }
+
+// Polls of the bounded waits (team barriers, loss helpers) before they give up; 0: the default.
+std::atomic<int32_t> g_wait_limit{0};
+
+int32_t wait_limit() {
+  const int32_t v = g_wait_limit.load(std::memory_order_relaxed);
+  return v > 0 ? v : kTeamSpinLimit;
+}
+
+// Waits for the fit and maps its status word: a bounded wait that gave up is HSIM_ETIMEOUT.
+int read_status(const int32_t* status_dev, hipStream_t s) {
+  int32_t st = 0;
+  hipError_t e = hipMemcpyAsync(&st, status_dev, sizeof(st), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return device_error(e, "regression status read");
+  if (st != 0)
+    return fail(HSIM_ETIMEOUT, "a bounded wait of the regression gave up (%s): the fit is incomplete",
+                (st & 1) ? "team barrier" : "loss snapshot");
+  return HSIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int hsim_set_wait_limit(int32_t polls) {
+  if (polls < 0) return fail(HSIM_EINVAL, "polls must be >= 0");
+  g_wait_limit.store(polls, std::memory_order_relaxed);
+  return HSIM_OK;
+}
+
+int cva_regress_adam_state(const cva_mlp_cfg* c, int32_t n_reg, int64_t M, const void* workspace_dev, size_t ws_bytes,
+                           float* params_dev, float* m_dev, float* v_dev, void* stream) {
+  if (cva_regress_workspace_bytes(c, n_reg, M) == 0) return fail(HSIM_EINVAL, "bad cfg or n_reg");
+  if (!workspace_dev || ws_bytes < cva_regress_workspace_bytes(c, n_reg, M))
+    return fail(HSIM_ENOWS, "workspace smaller than the fit's");
+  const size_t bytes = (size_t)MlpLayout{c->width, c->hidden}.n_params() * n_reg * sizeof(float);
+  const float* src = (const float*)workspace_dev;
+  float* dst[3] = {params_dev, m_dev, v_dev};
+  for (int k = 0; k < 3; ++k) {
+    if (!dst[k]) continue;
+    const hipError_t e = hipMemcpyAsync(dst[k], (const char*)src + k * bytes, bytes, hipMemcpyDeviceToDevice,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "Adam state copy");
+  }
+  return HSIM_OK;
+}
+
+int cva_regress_param_floats(const cva_mlp_cfg* c) {
+  int rc = check_cfg(c);
+  if (rc) return rc;
+  return MlpLayout{c->width, c->hidden}.n_params();
+}
 
 int cva_regress_record_floats(const cva_mlp_cfg* c) {
   int rc = check_cfg(c);
@@ -151,6 +203,8 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
   a.loss_part = (double*)w;
   w += ws.loss;
   a.team_ctr = (int32_t*)w;
+  a.status = a.team_ctr + n_teams;
+  a.spin_limit = wait_limit();
   w += ws.ctr;
   a.G = G;
   a.n_teams = n_teams;
@@ -174,13 +228,16 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_mlp_stats(a, s);
+  hipLaunchKernelGGL(zero_word, dim3(1), dim3(1), 0, s, a.status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return device_error(e, "status reset");
+  e = launch_mlp_stats(a, s);
   if (e != hipSuccess) return device_error(e, "regression statistics launch");
   if (!c->warm_start) {
     a.use_init = 0;
     e = launch_mlp_train(a, s);
     if (e != hipSuccess) return device_error(e, "regression training launch");
-    return HSIM_OK;
+    return read_status(a.status, s);
   }
   // Backward learning: dates in the given order, each started from the previous result.
   for (int j = 0; j < n_reg; ++j) {
@@ -201,7 +258,7 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
     e = launch_mlp_train(b, s);
     if (e != hipSuccess) return device_error(e, "regression training launch");
   }
-  return HSIM_OK;
+  return read_status(a.status, s);
 }
 
 int cva_regress_predict(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int32_t n_dates_total, int64_t M,

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhsim.so")
 HSIM_FP64, HSIM_FP32 = 0, 1
 FEAT_FACTORS, FEAT_FACTORS_PLUS = 0, 1
 OP_INNER, OP_TARGETS, OP_FUSED, OP_ADJOINT, OP_BRANCH = 1, 2, 3, 4, 5
+HSIM_ETIMEOUT = -6
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_f64p = ctypes.POINTER(ctypes.c_double)
@@ -94,6 +95,7 @@ def lib():
         "hsim_n_params": (ctypes.c_int, [M_]),
         "cva_adjoint": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, vp, vp, vp, sz, vp]),
         "cva_regress_record_floats": (ctypes.c_int, [ctypes.POINTER(MlpCfg)]),
+        "cva_regress_param_floats": (ctypes.c_int, [ctypes.POINTER(MlpCfg)]),
         "cva_regress_workspace_bytes": (sz, [ctypes.POINTER(MlpCfg), i32, i64]),
         "cva_regress_fit": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, _c_i32p, i32, i64, i32, vp,
                                            vp, vp, u64, vp, vp, vp, sz, vp]),
@@ -108,6 +110,8 @@ def lib():
         "hsim_branch_errors": (ctypes.c_int, [i64, i32, ctypes.c_int, vp, vp, vp, vp, sz, vp]),
         "cva_adjoint_forward": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i64, i32, vp, vp, vp, vp, vp,
                                                vp, vp, sz, vp]),
+        "cva_regress_adam_state": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, i64, vp, sz, vp, vp, vp, vp]),
+        "hsim_set_wait_limit": (ctypes.c_int, [i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -516,6 +520,24 @@ def regress_fit(cfg: MlpCfg, dates, X, Y, seed: int = 0, want_loss: bool = True,
                                 _dptr(X), _dptr(Y), _dptr(W), seed, _dptr(model), _dptr(loss), _dptr(ws), wsb,
                                 _stream()))
     return model, loss, ws
+
+
+def regress_adam_state(cfg: MlpCfg, n_reg: int, M: int, ws):
+    """cva_regress_adam_state: (params, m, v) [n_reg][n_params] after a fit on workspace ws."""
+    import torch
+    L = lib()
+    npar = L.cva_regress_param_floats(ctypes.byref(cfg))
+    if npar < 0:
+        check(npar)
+    out = [torch.empty((n_reg, npar), dtype=torch.float32, device="cuda") for _ in range(3)]
+    check(L.cva_regress_adam_state(ctypes.byref(cfg), n_reg, M, _dptr(ws), ws.numel(), _dptr(out[0]),
+                                   _dptr(out[1]), _dptr(out[2]), _stream()))
+    return tuple(out)
+
+
+def set_wait_limit(polls: int):
+    """hsim_set_wait_limit: polls before the regression's bounded waits give up (0: default)."""
+    check(lib().hsim_set_wait_limit(int(polls)))
 
 
 def regress_predict(cfg: MlpCfg, dates, X, model):
