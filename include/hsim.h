@@ -188,6 +188,18 @@ int hsim_targets_cva(const hsim_grid* grid, int32_t n_cpty, int64_t M, int32_t n
                      void* target_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,
                      void* stream);
 
+/* hsim_targets_cva for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same computation and results, with the
+ * FP64 block partials of CVA_0 kept in a static device array that the library holds on every GPU
+ * it runs on until the process ends (512 KiB), so no workspace is passed and nothing is
+ * allocated.  M <= 2^24 paths (HSIM_ERANGE beyond).  All calls on one GPU share that array: calls
+ * that overlap on one GPU (concurrent streams, threads) race and must be ordered by the caller.
+ * Other arguments as hsim_targets_cva. */
+int hsim_targets_cva_noalloc(const hsim_grid* grid, int32_t n_cpty, int64_t M, int32_t n_b,
+                             const int32_t* n_b_per_block, int32_t block_paths, int precision,
+                             const double* I_dev, const void* D_dev, const int32_t* counts_dev,
+                             void* target_dev, double* cva0_dev, void* stream);
+
 /* The paper's per-inner-sample regression data (Section 3.2: Algorithm 2 on the hierarchical
  * sample I = {paths} x {draws}, inputs (X_i, Y_i) with X the default indicators).  For every
  * outer path k of [path_begin, path_begin + M) and inner draw l < n_b (the draws of

@@ -351,6 +351,36 @@ int run_targets(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b, cons
   return HSIM_OK;
 }
 
+// ---------------------------------------------------------------------------- static scratch
+// Device memory of hsim_targets_cva_noalloc: the FP64 block partials of CVA_0 for up to
+// kNoAllocMaxPaths paths.  Every GPU the library runs on holds its own copy of the array until the
+// process ends; host code reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is a host-side stand-in, not a device address).
+constexpr int64_t kNoAllocMaxPaths = (int64_t)1 << 24;
+constexpr size_t kScratchDoubles = (size_t)((kNoAllocMaxPaths + kTargetBlock - 1) / kTargetBlock);
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// Address of `scratch` on the current device, looked up once per device with that device current.
+int scratch_address(double** out) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(HSIM_ERANGE, "device ordinal %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return device_error(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(HSIM_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    addr[dev] = (double*)p;
+  }
+  *out = addr[dev];
+  return HSIM_OK;
+}
+
 }  // namespace hsim
 
 using namespace hsim;
@@ -472,6 +502,30 @@ int hsim_targets_cva(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b,
                                   target_dev, cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream)
              : run_targets<double>(g, n_cpty, M, n_b, n_b_per_block, block_paths, I_dev, D_dev, counts_dev,
                                    target_dev, cva0_dev, workspace_dev, ws_bytes, (hipStream_t)stream);
+}
+
+int hsim_targets_cva_noalloc(const hsim_grid* g, int32_t n_cpty, int64_t M, int32_t n_b,
+                             const int32_t* n_b_per_block, int32_t block_paths, int precision, const double* I_dev,
+                             const void* D_dev, const int32_t* counts_dev, void* target_dev, double* cva0_dev,
+                             void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if ((rc = check_precision(precision))) return rc;
+  if ((rc = check_paths(0, M))) return rc;
+  if (M > kNoAllocMaxPaths)
+    return fail(HSIM_ERANGE, "M = %lld exceeds the %lld paths of the static scratch (use hsim_targets_cva)",
+                (long long)M, (long long)kNoAllocMaxPaths);
+  if ((rc = check_nb(n_b, n_b_per_block, block_paths))) return rc;
+  if (n_cpty < 1 || n_cpty > HSIM_MAX_CPTY) return fail(HSIM_ERANGE, "n_cpty out of range");
+  if (!I_dev || !D_dev || !counts_dev || !target_dev || !cva0_dev) return fail(HSIM_EINVAL, "NULL array");
+  double* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  const size_t ws_bytes = kScratchDoubles * sizeof(double);
+  return precision == HSIM_FP32
+             ? run_targets<float>(g, n_cpty, M, n_b, n_b_per_block, block_paths, I_dev, D_dev, counts_dev,
+                                  target_dev, cva0_dev, ws, ws_bytes, (hipStream_t)stream)
+             : run_targets<double>(g, n_cpty, M, n_b, n_b_per_block, block_paths, I_dev, D_dev, counts_dev,
+                                   target_dev, cva0_dev, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int hsim_sample_rows(const hsim_grid* g, int32_t n_cpty, int32_t d, uint64_t seed, int64_t path_begin, int64_t M,

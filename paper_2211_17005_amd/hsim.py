@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhsim.so")
 HSIM_FP64, HSIM_FP32 = 0, 1
 FEAT_FACTORS, FEAT_FACTORS_PLUS = 0, 1
 OP_INNER, OP_TARGETS, OP_FUSED, OP_ADJOINT, OP_BRANCH = 1, 2, 3, 4, 5
-HSIM_ETIMEOUT = -6
+HSIM_EINVAL, HSIM_ERANGE, HSIM_ENOWS, HSIM_EDEVICE, HSIM_EUNSUPPORTED, HSIM_ETIMEOUT = -1, -2, -3, -4, -5, -6
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_f64p = ctypes.POINTER(ctypes.c_double)
@@ -86,6 +86,8 @@ def lib():
                                                sz, vp]),
         "hsim_targets_cva": (ctypes.c_int, [G_, i32, i64, i32, vp, i32, ctypes.c_int, vp, vp, vp,
                                             vp, vp, vp, sz, vp]),
+        "hsim_targets_cva_noalloc": (ctypes.c_int, [G_, i32, i64, i32, vp, i32, ctypes.c_int, vp, vp,
+                                                    vp, vp, vp, vp]),
         "hsim_targets_intensity": (ctypes.c_int, [G_, i32, i64, ctypes.c_int, vp, vp, vp, vp, vp,
                                                   vp, sz, vp]),
         "hsim_inner_defaults_cva": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i32, vp, i32,
@@ -318,6 +320,25 @@ def targets_cva(grid, n_cpty: int, I, D, counts, n_b: int = 1, n_b_per_block=Non
     check(lib().hsim_targets_cva(ctypes.byref(g), n_cpty, M, nb, _dptr(nbt), bp, precision,
                                  _dptr(I), _dptr(D), _dptr(counts), _dptr(T), _dptr(cva0),
                                  _dptr(ws), wsb, _stream()))
+    torch.cuda.current_stream().synchronize() if nbt is not None else None
+    return T, cva0
+
+
+def targets_cva_noalloc(grid, n_cpty: int, I, D, counts, n_b: int = 1, n_b_per_block=None,
+                        block_paths: int = 64, precision: int = HSIM_FP32):
+    """hsim_targets_cva_noalloc: targets_cva without a workspace (the library's static scratch)."""
+    import torch
+    M = I.shape[-1]
+    _expect(I, torch.float64, (grid.n_dates + 1, M), "I")
+    _expect(D, _real(precision), (grid.n_dates + 1, n_cpty, M), "D")
+    _expect(counts, torch.int32, (grid.n_dates + 1, n_cpty, M), "counts")
+    T = torch.empty((grid.n_dates + 1, M), dtype=_real(precision), device="cuda")
+    cva0 = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = grid_struct(grid)
+    nb, nbt, bp = _nb_args(n_b, n_b_per_block, block_paths)
+    check(lib().hsim_targets_cva_noalloc(ctypes.byref(g), n_cpty, M, nb, _dptr(nbt), bp, precision,
+                                         _dptr(I), _dptr(D), _dptr(counts), _dptr(T), _dptr(cva0),
+                                         _stream()))
     torch.cuda.current_stream().synchronize() if nbt is not None else None
     return T, cva0
 
