@@ -174,8 +174,18 @@ def cpu_baseline(w, name, kw, workers: int, n_sim: int, n_rows: int, n_sens: int
            + t_reg * (dates * w.M * wr.mlp.epochs) / (workers * n_rows * 1)
            + t_sens * (2 * n_par * ws.M) / (workers * n_sens))
     rate = w.M * w.n_b * w.grid.n_dates / est
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": rate, "unit": "path-steps/s", "cores": workers, "kind": "oracle",
             "est_solve_s": est,
+            "host": {"nproc": os.cpu_count(), "cpu_model": model, "processes": workers,
+                     "note": "one process per core of the GPU's host share (16 per GPU)"},
             "sample": f"{workers} processes in parallel, each: simulation of {n_sim} outer paths "
                       f"x n_b={w.n_b} ({t_sim:.1f} s), one BaseAlg epoch on {n_rows} rows of one "
                       f"date ({t_reg:.1f} s), CVA_0 of {n_sens} sensitivity paths ({t_sens:.1f} s); "
@@ -185,61 +195,83 @@ def cpu_baseline(w, name, kw, workers: int, n_sim: int, n_rows: int, n_sens: int
 
 
 # ------------------------------------------------------------------------------- plain FP32
-def plain_regression_fp32(X, Y, mlp, dates, seed):
-    """Comparator: BaseAlg + Backward learning in plain FP32 PyTorch, one date after another."""
-    import torch
-    from oracle import regression as org     # initial draw only (same as the library's)
-    dev = X.device
-    d_in = X.shape[1]
-    M = X.shape[2]
-    batch = mlp.batch
-    net0 = org.init_net(d_in, mlp.hidden, mlp.width, seed)
-    Ws = [torch.tensor(w, dtype=torch.float32, device=dev) for w in net0.W]
-    bs = [torch.zeros(w.shape[0], dtype=torch.float32, device=dev) for w in net0.W]
-    mu = torch.zeros((), dtype=torch.float32, device=dev)
-    for i in dates:
-        x = X[i].T
-        y = Y[i]
-        xs = (x - x.mean(0)) / x.std(0, unbiased=False).clamp_min(1e-30)
-        ys = torch.sqrt((y * y).mean())
-        yn = y / ys
-        params = [p.clone().requires_grad_(True) for p in Ws + bs] + [mu.clone().requires_grad_(True)]
-        opt = torch.optim.Adam(params, lr=mlp.lr, betas=(mlp.beta1, mlp.beta2), eps=mlp.eps)
-        H = mlp.hidden
+def plain_fp32_solve(hsim, torch, w, wr, wa, fixed, fast):
+    """The plain FP32 form of the same solve, all in the library, timed stage by stage:
+    simulation with FP32 integrals (HSIM_FP32_PLAIN, separate stages), Backward learning
+    (Algorithm 2) over every trained date with the FP32 GEMM regression (REG_FP32), and CVA_0
+    sensitivities by central differences with common random numbers (relative bump 1e-4) of the
+    smoothed estimator on the plain simulation of the sensitivity paths.  Then the accuracy of the
+    two forms side by side: CVA_0 against one Monte Carlo standard error, the held-out mean
+    squared error of the two regressions on out-of-sample paths, and the finite differences
+    against the adjoint gradient."""
+    M, n1, C = w.M, w.grid.n_dates + 1, w.market.n_cpty
+    d = wl.n_features(w)
+    dates = list(range(w.grid.n_dates - 1, 0, -1))
 
-        def f(xx, p):
-            a = xx
-            for l in range(H):
-                a = torch.relu(a @ p[l].T + p[H + 1 + l])
-            return (a @ p[H].T + p[2 * H + 1])[:, 0], a
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
 
-        best, pos = float("inf"), 0
-        for epoch in range(1, mlp.epochs + 1):
-            for s in range(0, M, batch):
-                out, _ = f(xs[s:s + batch], params)
-                pred = (torch.relu(out) if pos else out) + params[-1]
-                loss = ((pred - yn[s:s + batch]) ** 2).mean()
-                opt.zero_grad()
-                loss.backward()
-                opt.step()
-            with torch.no_grad():
-                if epoch == mlp.epochs // 2:
-                    _, a = f(xs, params)
-                    A = torch.cat([a, torch.ones_like(a[:, :1])], 1)
-                    G = A.T @ A
-                    lam = 1e-4 * torch.trace(G) / G.shape[0]
-                    sol = torch.linalg.solve(G + lam * torch.eye(G.shape[0], device=dev),
-                                             A.T @ (yn - params[-1]))
-                    params[H].copy_(sol[:-1][None, :])
-                    params[2 * H + 1].copy_(sol[-1:])
-                    pos = 1
-                out, _ = f(xs, params)
-                L = float((((torch.relu(out)) + params[-1] - yn) ** 2).mean())
-                if L < best:
-                    best = L
-                    kept = [p.detach().clone() for p in params]
-        Ws, bs, mu = kept[:H + 1], kept[H + 1:2 * H + 2], kept[-1]
-    torch.cuda.synchronize()
+    sol = hsim.Solver(w, precision=hsim.HSIM_FP32_PLAIN, fixed=fixed)
+    sol.inner_defaults_cva()                                   # untimed first call
+    (feats, T, cva0), sim_s = timed(sol.inner_defaults_cva)
+    cfg = hsim.mlp_cfg(wr.mlp, d, M, warm_start=True, dtype=hsim.REG_FP32)
+    (model, _, _), reg_s = timed(lambda: hsim.regress_fit(cfg, dates, feats, T, seed=w.seed, want_loss=False))
+
+    base = hsim.pack_params(wa.market)
+    h = 1e-4
+
+    def fd():
+        g = np.zeros(base.size)
+        for k in range(base.size):
+            step = h * abs(base[k]) if base[k] != 0 else h
+            v = []
+            for sgn in (1.0, -1.0):
+                b = base.copy()
+                b[k] += sgn * step
+                o = hsim.outer_paths(wa, precision=hsim.HSIM_FP32_PLAIN, want_features=False, fixed=fixed,
+                                     market=hsim.unpack_params(wa.market, b))
+                v.append(hsim.targets_intensity(wa.grid, C, o["I"], o["Lam"], o["D"])[1].item())
+            g[k] = (v[0] - v[1]) / (2.0 * step)
+        return g
+    g_fd, fd_s = timed(fd)
+    plain_s = sim_s + reg_s + fd_s
+
+    # accuracy: CVA_0 within one standard error of the fast form's estimator
+    T0 = fast["T"][0].double()
+    se = float(T0.std() / np.sqrt(M))
+    d_cva = abs(cva0.item() - fast["cva0"])
+    # held-out regression error: out-of-sample paths, targets of the fast simulation
+    Mh = 1 << 14
+    hold = hsim.Solver(w, precision=hsim.HSIM_FP32, M=Mh, fixed=fixed)
+    hf, hT, _ = hold.inner_defaults_cva(path_begin=M)
+    pf = hsim.regress_predict(fast["cfg"], fast["dates"], hf, fast["model"])
+    order = [fast["dates"].index(i) for i in dates]
+    mse_fast = float(((pf[order].double() - hT[dates].double()) ** 2).mean())
+    pp = hsim.regress_predict(cfg, dates, hf, model)
+    mse_plain = float(((pp.double() - hT[dates].double()) ** 2).mean())
+    # gradients: finite differences against the adjoint, per component
+    g_adj = fast["grad"]
+    scale = np.maximum(np.abs(g_adj), 1e-3 * np.max(np.abs(g_adj)))
+    gerr = np.abs(g_fd - g_adj) / scale
+    names = [f"{f}[{i}]" for f in hsim.PARAM_FIELDS for i in range(len(np.atleast_1d(getattr(wa.market, f))))]
+    return {"solve_s": plain_s, "simulation_s": sim_s, "regression_s": reg_s, "sensitivities_s": fd_s,
+            "speedup_of_fast_form": plain_s / fast["solve_s"],
+            "forms": {"simulation": "f32 with f32 integrals, separate stages",
+                      "regression": f"REG_FP32 rocBLAS path, Algorithm 2 over {len(dates)} dates",
+                      "sensitivities": f"central differences, 2 x {base.size} simulations of {wa.M} paths, "
+                                       f"h = {h:g} relative, common random numbers"},
+            "accuracy": {"cva0_fast": fast["cva0"], "cva0_plain": cva0.item(), "cva0_se": se,
+                         "cva0_diff_in_se": d_cva / se,
+                         "heldout_paths": Mh, "heldout_mse_fast": mse_fast, "heldout_mse_plain": mse_plain,
+                         "heldout_mse_rel_diff": (mse_plain - mse_fast) / mse_fast,
+                         "grad_max_scaled_err": float(gerr.max()),
+                         "grad_worst": names[int(np.argmax(gerr))],
+                         "grad_components_over_1e-3": int((gerr > 1e-3).sum()),
+                         "equal": bool(d_cva <= se and abs(mse_plain - mse_fast) <= 0.02 * mse_fast)}}
 
 
 # ------------------------------------------------------------------------------- sweep
@@ -265,6 +297,29 @@ def oversim_sweep(hsim, torch, M: int, reps: int = 3):
     steps = float(nb_paths.sum()) * w.grid.n_dates
     return {"workload": w.name, "M": M, "levels": list(wl.OVERSIM_LEVELS), "block_paths": 64,
             "ms_per_call": ms, "path_steps_per_s": steps / (ms / 1e3), "dtype": "f32 (f64 integrals)"}
+
+
+def variance_report(hsim, torch, Ms=(1 << 14, 1 << 16, 1 << 18, 1 << 20), date_years: float = 5.0):
+    """The batched oversimulation configuration's variance report: on the plain-case market, for
+    every M and uniform n_b of the sweep, the sample variance over the outer paths of the target
+    T_i at t = 5y, and per M the least-squares fit Var = R + Q / n_b (Section 3.3: the part of the
+    variance due to the inner draws falls as 1 / n_b)."""
+    out = []
+    for M in Ms:
+        rows = []
+        for nb in wl.OVERSIM_LEVELS:
+            w = wl.plain_fp64().with_(M=M, n_b=nb)
+            i = int(round(date_years / w.grid.horizon * w.grid.n_dates))
+            s = hsim.Solver(w, precision=hsim.HSIM_FP32)
+            _, T, _ = s.inner_defaults_cva(want_features=False)
+            rows.append(float(T[i].double().var()))
+            del s, T
+        A = np.stack([np.ones(len(rows)), 1.0 / np.asarray(wl.OVERSIM_LEVELS, dtype=np.float64)], 1)
+        (R, Q), *_ = np.linalg.lstsq(A, np.asarray(rows), rcond=None)
+        out.append({"M": M, "date": i, "var_T": dict(zip([str(n) for n in wl.OVERSIM_LEVELS], rows)),
+                    "fit_R": float(R), "fit_Q": float(Q)})
+    torch.cuda.synchronize()
+    return out
 
 
 # ------------------------------------------------------------------------------- validation
@@ -320,7 +375,6 @@ def main():
     ap.add_argument("--sweep-M", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (scale of the FETCH/WRITE counters)")
-    ap.add_argument("--plain-dates", type=int, default=2)
     ap.add_argument("--no-validation", action="store_true",
                     help="skip the twin / nested Monte Carlo check of the fitted network")
     args = ap.parse_args()
@@ -465,34 +519,16 @@ def main():
 
     plain = None
     if not args.sim_only and not args.no_plain:
-        # plain FP32 form: same simulation; sequential FP32 regression in PyTorch (timed on a
-        # few dates and scaled to all of them); sensitivities by CRN central differences
-        pd = list(range(w.grid.n_dates - 1, w.grid.n_dates - 1 - args.plain_dates, -1))
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        plain_regression_fp32(feats, T, wr.mlp, pd, w.seed)
-        reg_s = (time.perf_counter() - t) * (w.grid.n_dates - 1) / len(pd)
-        base = hsim.pack_params(wa.market)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for k in range(base.size):
-            h = 1e-3 * abs(base[k]) if base[k] != 0 else 1e-4
-            for sgn in (1.0, -1.0):
-                v = base.copy()
-                v[k] += sgn * h
-                adj(hsim.unpack_params(wa.market, v), with_grad=False)
-        torch.cuda.synchronize()
-        fd_s = time.perf_counter() - t
-        sim_s = (stage_ms["outer"] + stage_ms["inner"] + stage_ms["targets"]) / 1e3
-        plain_s = sim_s + reg_s + fd_s
-        plain = {"solve_s": plain_s, "simulation_s": sim_s,
-                 "regression_s": reg_s, "regression_note": f"timed on {len(pd)} dates, scaled to "
-                 f"{w.grid.n_dates - 1}", "sensitivities_s": fd_s,
-                 "speedup_of_fast_form": plain_s / (ms_step / 1e3)}
+        cva_fast, grad_fast = adj.from_forward(feats, I, Lam, D)
+        fast = {"T": T, "cva0": cva0.item(), "cfg": cfg, "dates": dates, "model": model,
+                "grad": grad_fast.cpu().numpy().copy(), "solve_s": ms_step / 1e3}
+        plain = plain_fp32_solve(hsim, torch, w, wr, wa, fixed, fast)
+        print(f"# plain FP32 form: {plain['solve_s']:.2f} s per solve", file=sys.stderr, flush=True)
 
     sweep = None
     if not args.sim_only and not args.no_sweep:
         sweep = oversim_sweep(hsim, torch, args.sweep_M)
+        sweep["variance_at_5y"] = variance_report(hsim, torch)
 
     valid = None
     if not args.sim_only and not args.no_validation:

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define HSIM_ABI_VERSION 1
+#define HSIM_ABI_VERSION 2
 
 enum hsim_status {
   HSIM_OK = 0,
@@ -60,8 +60,11 @@ enum hsim_status {
 
 /* Arithmetic of the simulation.  HSIM_FP64: all state and prices in FP64.  HSIM_FP32:
  * state, normals and prices in FP32; the integrals int r^0 and int gamma^c (hence
- * beta and Lambda) are always accumulated in FP64. */
-enum hsim_precision { HSIM_FP64 = 0, HSIM_FP32 = 1 };
+ * beta and Lambda) are accumulated in FP64.  HSIM_FP32_PLAIN (hsim_outer_paths and
+ * hsim_inner_defaults_cva only; the baseline the FP64-integral form is measured against): as
+ * HSIM_FP32 but the integrals, beta and the exposures' discounting are FP32 too; its outputs have
+ * the FP32 types (I and Lambda are still written as double). */
+enum hsim_precision { HSIM_FP64 = 0, HSIM_FP32 = 1, HSIM_FP32_PLAIN = 2 };
 
 /* Regression inputs emitted per date.  FACTORS: r^0..r^{n_e-1}, log chi^1..log chi^{n_e-1},
  * gamma^1..gamma^C (the diffusive factors of Section 4.3).  FACTORS_PLUS adds
@@ -252,6 +255,23 @@ int hsim_inner_defaults_cva(const hsim_market* market, const hsim_portfolio* boo
                             void* target_dev, double* cva0_dev, void* workspace_dev,
                             size_t ws_bytes, void* stream);
 
+/* The whole simulation in one launch (Section 3.2's hierarchical sample, Appendix B, Section 4.2
+ * eq:CVA_portfolio): outer paths, inner default draws and targets with the results of
+ * hsim_outer_paths (features), hsim_inner_defaults and hsim_targets_cva bit for bit.  One
+ * workgroup of 64 lanes per tile of 64 outer paths simulates them one lane per path (state in
+ * registers) and writes, per path and date, the integer default thresholds of the rule
+ * Lambda^c_j >= -log u, the exposures D^c_j and I_j into a path-major table in the workspace; the
+ * same workgroup then draws each path's n_b x C inner defaults cooperatively (lanes = draws, the
+ * default dates counted in an LDS histogram) and forms its targets.  I, Lambda, D and the counts
+ * never reach the caller (hsim_inner_defaults_cva's date-major round trip), and the table is
+ * about half their size.  Arguments as hsim_inner_defaults_cva (precision HSIM_FP32 or HSIM_FP64);
+ * workspace hsim_workspace_bytes(HSIM_OP_FUSED_LAUNCH, ...).  HSIM_ERANGE when
+ * (n+1) x n_cpty is too large for the kernel's LDS (more than 64 KiB: the separate stages then). */
+int hsim_fused(const hsim_market* market, const hsim_portfolio* book, const hsim_grid* grid, uint64_t seed,
+               int64_t path_begin, int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
+               int precision, int feature_mode, void* features_dev, void* target_dev, double* cva0_dev,
+               void* workspace_dev, size_t ws_bytes, void* stream);
+
 /* Pilot moments of the oversimulation chooser (Section 3.3, Proposition p:heurisN).  For
  * every date i and path k of T1_dev / T2_dev [n+1][M] (the n_b = 1 and n_b = 2 targets of
  * one seed, float if FP32 else double; with the common random numbers of
@@ -262,6 +282,25 @@ int hsim_inner_defaults_cva(const hsim_market* market, const hsim_portfolio* boo
  * R = E[g g'] - E[g]^2 and Q = E[g^2] - E[g g'] give N*_i = sqrt(Q_i P / R_i) (e:optom). */
 int hsim_oversim_moments(const hsim_grid* grid, int64_t M, int precision, const void* T1_dev,
                          const void* T2_dev, const void* pred_dev, double* moments_dev, void* stream);
+
+/* Cost ratio of Section 3.3 (l:ratio): P, the cost of one outer path in units of one inner
+ * continuation, from the times t and t_prime of two simulations with the same number of outer
+ * paths and N, N_prime inner draws (t / t' = (P + N) / (P + N')):
+ *   P = (t' N - t N') / (t - t').
+ * Host arithmetic.  HSIM_EINVAL if a time is not positive, N == N_prime, t == t_prime, or P is not
+ * positive and finite (timings that do not resolve the ratio). */
+int hsim_oversim_cost_ratio(double t, double t_prime, double N, double N_prime, double* P_out);
+
+/* Heuristic heur:MN of Section 3.3 from the pilot moments of hsim_oversim_moments (host copy,
+ * [n_dates1][3]: E[g], E[g^2], E[g g'] per date): R_i = E[g g'] - E[g]^2,
+ * Q_i = E[g^2] - E[g g'], N*_i = sqrt(Q_i P / R_i) (Proposition p:heurisN, e:optom) at every date
+ * with R_i > 0 and Q_i >= 0 (NaN elsewhere, e.g. dates after the last maturity, which carry no
+ * loss); N = the mean of the defined N*_i, at least 1 (1 if none is defined); M = Psi / (N + P)
+ * outer paths for a budget of Psi inner-continuation units.  Host arrays R_out, Q_out, Nstar_out
+ * [n_dates1] may be NULL.  Writes N and M; returns the number of dates with a defined N*_i, or
+ * HSIM_EINVAL (P <= 0, Psi <= 0, n_dates1 < 1, NULL moments or outputs). */
+int hsim_oversim_choose(int32_t n_dates1, const double* moments_host, double P, double Psi,
+                        double* R_out, double* Q_out, double* Nstar_out, double* N_out, double* M_out);
 
 /* Branched re-simulation (Section 3.3 twin Monte Carlo validation, e:val1/e:val2; the
  * nested Monte Carlo benchmark of Section 4.3 on eq:CVAint).  For every outer path k of
@@ -292,7 +331,7 @@ int hsim_branch_errors(int64_t M, int32_t n_branch, int precision, const void* p
                        void* stream);
 
 enum hsim_op { HSIM_OP_INNER = 1, HSIM_OP_TARGETS = 2, HSIM_OP_FUSED = 3, HSIM_OP_ADJOINT = 4,
-               HSIM_OP_BRANCH = 5 };
+               HSIM_OP_BRANCH = 5, HSIM_OP_FUSED_LAUNCH = 6 };
 
 /* Device workspace (bytes) an operation needs for M paths and the given market/grid. */
 size_t hsim_workspace_bytes(int op, const hsim_market* market, const hsim_grid* grid,
@@ -326,7 +365,8 @@ typedef struct {
   int32_t d_in;       /* inputs per row, 1..32 (the first d_in features of X) */
   int32_t epochs;     /* E >= 1 */
   int32_t batch;      /* rows per SGD batch; the last batch of an epoch may be shorter */
-  float lr, beta1, beta2, eps;  /* Adam (lr >= 0; lr = 0 leaves the network as initialised) */
+  double lr, beta1, beta2, eps; /* Adam (lr >= 0; lr = 0 leaves the network as initialised); the
+                                   BF16 kernel uses them rounded to FP32 */
   int32_t warm_start; /* 0: every date trains independently from the same initial draw, all dates
                          in one persistent launch; 1: Backward learning, dates trained one after
                          another in the order given, each started from the previous date's result */
@@ -334,12 +374,22 @@ typedef struct {
   int32_t team;       /* workgroups training one date together (0..32); 0: chosen by the library
                          from the device size, the number of dates and the batch.  Results depend
                          on it only through the summation order of the batch gradient */
+  int32_t dtype;      /* HSIM_REG_BF16: the matrix-core kernel described above (BF16 weights and
+                         activations, FP32 accumulation), shapes as listed.  HSIM_REG_FP32 /
+                         HSIM_REG_FP64: every product a rocBLAS GEMM / GEMV and every other step in
+                         that precision (FP64 normal equations of the refit), dates trained one
+                         after another (team ignored), any width 1..128 with 1..3 hidden layers;
+                         X, Y, W, the model record and the loss history are then float (FP32) or
+                         double (FP64).  Same initial draw, readings and record layout in all three */
 } cva_mlp_cfg;
 
-/* Floats per date of the model array written by cva_regress_fit (parameters, then scaling). */
+enum { HSIM_REG_BF16 = 0, HSIM_REG_FP32 = 1, HSIM_REG_FP64 = 2 };
+
+/* Elements per date of the model array written by cva_regress_fit (parameters, then scaling); float
+ * for HSIM_REG_BF16 / HSIM_REG_FP32, double for HSIM_REG_FP64. */
 int cva_regress_record_floats(const cva_mlp_cfg* cfg);
 
-/* Floats of the parameters at the head of a model record, in the order
+/* Elements of the parameters at the head of a model record, in the order
  * W_1 [width][32] (columns >= d_in zero), b_1, W_2 [width][width], b_2, ..., W_hidden, b_hidden,
  * w_out [width], b_out, mu; the record continues with the input means [32], the inverse standard
  * deviations [32], the target scale and a trained flag. */
@@ -349,9 +399,9 @@ int cva_regress_param_floats(const cva_mlp_cfg* cfg);
 size_t cva_regress_workspace_bytes(const cva_mlp_cfg* cfg, int32_t n_reg, int64_t M);
 
 /* Fit one network per date j < n_reg on rows k < M of
- *   X_dev [n_dates_total][n_feat][M] (float, the features of hsim_outer_paths) and
- *   Y_dev [n_dates_total][M] (float, the targets of hsim_targets_cva),
- *   W_dev [n_dates_total][M] (float row weights >= 0, or NULL for all 1: every loss becomes
+ *   X_dev [n_dates_total][n_feat][M] (the features of hsim_outer_paths) and
+ *   Y_dev [n_dates_total][M] (the targets of hsim_targets_cva),
+ *   W_dev [n_dates_total][M] (row weights >= 0, or NULL for all 1: every loss becomes
  *   (1/rows) sum_k w_k (pred_k - y_k)^2 and the refit solves the weighted normal equations;
  *   with the weights of hsim_targets_alive this is the grouped form of the paper's
  *   per-inner-sample regression, Section 3.2),
@@ -360,27 +410,30 @@ size_t cva_regress_workspace_bytes(const cva_mlp_cfg* cfg, int32_t n_reg, int64_
  * full-sample loss after every epoch (in units of the scaled targets).  n_reg <= 512.
  * The team barriers and the loss helpers' waits are bounded: should one give up (it cannot while
  * every workgroup of the cooperative launch is resident), the fit stops early and the call
- * returns HSIM_ETIMEOUT.  Synchronous: returns once the fit on `stream` has completed. */
+ * returns HSIM_ETIMEOUT.  Element type of X, Y, W, model and loss history: float, or double for
+ * HSIM_REG_FP64.  Synchronous: returns once the fit on `stream` has completed. */
 int cva_regress_fit(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,
-                    int64_t M, int32_t n_feat, const float* X_dev, const float* Y_dev,
-                    const float* W_dev, uint64_t seed, float* model_dev, float* loss_hist_dev,
+                    int64_t M, int32_t n_feat, const void* X_dev, const void* Y_dev,
+                    const void* W_dev, uint64_t seed, void* model_dev, void* loss_hist_dev,
                     void* workspace_dev, size_t ws_bytes, void* stream);
 
 /* Test hook: after a cva_regress_fit call with the same cfg, n_reg and M on this workspace, copy
- * each date's last parameters and Adam moments (FP32, [n_reg][n_params] each, the parameter order
- * of the model record; any output may be NULL).  With epochs = 1 and batch = M they hold one
- * Adam step: m = (1 - beta1) g and v = (1 - beta2) g^2 of the full-sample gradient g. */
+ * each date's last parameters and Adam moments ([n_reg][n_params] each, float, or double for
+ * HSIM_REG_FP64, the parameter order of the model record; any output may be NULL).  With
+ * epochs = 1 and batch = M they hold one Adam step: m = (1 - beta1) g and v = (1 - beta2) g^2 of
+ * the full-sample gradient g. */
 int cva_regress_adam_state(const cva_mlp_cfg* cfg, int32_t n_reg, int64_t M, const void* workspace_dev,
-                           size_t ws_bytes, float* params_dev, float* m_dev, float* v_dev, void* stream);
+                           size_t ws_bytes, void* params_dev, void* m_dev, void* v_dev, void* stream);
 
 /* Test hook: the number of polls after which the regression's bounded waits give up (0 restores
  * the default, 2^22 polls of about a microsecond each).  Process-wide; affects later fits. */
 int hsim_set_wait_limit(int32_t polls);
 
-/* Predictions out_dev [n_reg][M] = ((f)^+ + mu) * y_scale of the fitted networks on X_dev. */
+/* Predictions out_dev [n_reg][M] = ((f)^+ + mu) * y_scale of the fitted networks on X_dev (float,
+ * or double for HSIM_REG_FP64, as the fit's). */
 int cva_regress_predict(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,
-                        int64_t M, int32_t n_feat, const float* X_dev, const float* model_dev,
-                        float* out_dev, void* stream);
+                        int64_t M, int32_t n_feat, const void* X_dev, const void* model_dev,
+                        void* out_dev, void* stream);
 
 
 /* ------------------------------------------------------------------------------------------

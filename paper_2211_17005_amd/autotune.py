@@ -75,7 +75,7 @@ def regression_team(cfg, dates, X, Y, seed: int = 0, candidates=CANDIDATES, forc
         t_e = {}
         for epochs in ((1, 3) if E > 1 else (1,)):
             trial = hsim.MlpCfg(cfg.hidden, cfg.width, cfg.d_in, epochs, cfg.batch, cfg.lr, cfg.beta1,
-                                cfg.beta2, cfg.eps, cfg.warm_start, cfg.init_tag, team)
+                                cfg.beta2, cfg.eps, cfg.warm_start, cfg.init_tag, team, cfg.dtype)
             if hsim.lib().cva_regress_workspace_bytes(ctypes.byref(trial), n_dates, M) == 0:
                 break                                  # does not fit on the device
             best = float("inf")

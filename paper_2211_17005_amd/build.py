@@ -1,4 +1,7 @@
-"""Build libhsim.so (the HIP kernels and the C-ABI) in-tree for gfx950 with hipcc."""
+"""Build libhsim.so (the HIP kernels and the C-ABI) in-tree for gfx950 with hipcc.
+
+Every source is compiled to an object in parallel (relocatable device code is not needed: each
+kernel is launched from the file that defines it), then linked with rocBLAS into the library."""
 from __future__ import annotations
 
 import glob
@@ -6,14 +9,16 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsim.so")
+OBJ = os.path.join(ROOT, "_build")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 VALU forms stay off in every kernel of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wno-unused-command-line-argument",
@@ -31,16 +36,34 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def _compile(src: str, verbose: bool):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    return src, obj, p
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libhsim.so next to this file; returns its path."""
+    """Compile every HIP source and link libhsim.so next to this file; returns its path."""
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))
+    with ThreadPoolExecutor(max_workers=max(1, min(jobs, 16))) as ex:
+        results = list(ex.map(lambda s: _compile(s, verbose), sources()))
+    bad = [(s, p) for s, _, p in results if p.returncode != 0]
+    for s, p in bad:
+        sys.stderr.write(f"== {s}\n{p.stdout}{p.stderr}")
+    if bad:
+        raise RuntimeError("hipcc failed building libhsim.so")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")] + sources() + ["-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for _, o, _ in results] + ["-lrocblas", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         sys.stderr.write(p.stdout + p.stderr)
-        raise RuntimeError("hipcc failed building libhsim.so")
+        raise RuntimeError("linking libhsim.so failed")
     os.replace(tmp, LIB)
     return LIB
 

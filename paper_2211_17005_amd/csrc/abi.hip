@@ -311,7 +311,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 template <typename Real>
 int run_outer(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed,
               int64_t path_begin, int64_t M, int feature_mode, void* features, double* I, double* Lam,
-              void* D, void* MtM, hipStream_t stream) {
+              void* D, void* MtM, hipStream_t stream, bool fp32_integrals = false) {
   SimArgs<Real> a;
   int rc = build_sim_args<Real>(m, p, g, seed, path_begin, M, feature_mode, a);
   if (rc) return rc;
@@ -320,7 +320,7 @@ int run_outer(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g,
   a.Lam = Lam;
   a.D = (Real*)D;
   a.MtM = (Real*)MtM;
-  hipError_t e = launch_outer<Real>(a, stream);
+  hipError_t e = launch_outer<Real>(a, stream, fp32_integrals);
   if (e != hipSuccess) return device_error(e, "outer kernel launch");
   return HSIM_OK;
 }
@@ -441,12 +441,13 @@ int hsim_normals_fill(uint64_t seed, int64_t path_begin, int64_t count, int32_t 
 int hsim_outer_paths(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed,
                      int64_t path_begin, int64_t M, int precision, int feature_mode, void* features_dev,
                      double* I_dev, double* Lambda_dev, void* D_dev, void* MtM_dev, void* stream) {
-  int rc = check_precision(precision);
+  const bool plain = precision == HSIM_FP32_PLAIN;
+  int rc = plain ? HSIM_OK : check_precision(precision);
   if (rc) return rc;
   if (!I_dev || !Lambda_dev || !D_dev) return fail(HSIM_EINVAL, "I, Lambda and D outputs must not be NULL");
-  return precision == HSIM_FP32
+  return precision != HSIM_FP64
              ? run_outer<float>(m, p, g, seed, path_begin, M, feature_mode, features_dev, I_dev, Lambda_dev,
-                                D_dev, MtM_dev, (hipStream_t)stream)
+                                D_dev, MtM_dev, (hipStream_t)stream, plain)
              : run_outer<double>(m, p, g, seed, path_begin, M, feature_mode, features_dev, I_dev, Lambda_dev,
                                  D_dev, MtM_dev, (hipStream_t)stream);
 }
@@ -673,14 +674,66 @@ size_t hsim_workspace_bytes(int op, const hsim_market* m, const hsim_grid* g, in
     case HSIM_OP_FUSED: {
       if (!m) return 0;
       const size_t C = (size_t)m->n_cpty;
-      const size_t rs = precision == HSIM_FP32 ? sizeof(float) : sizeof(double);
+      const size_t rs = precision == HSIM_FP64 ? sizeof(double) : sizeof(float);
       return align256(n1 * M * sizeof(double)) + align256(n1 * C * M * sizeof(double)) +
              align256(n1 * C * M * rs) + align256(n1 * C * M * sizeof(int32_t)) + partial +
              align256(inner_order_bytes(M));
     }
+    case HSIM_OP_FUSED_LAUNCH: {
+      if (!m) return 0;
+      const size_t nc = n1 * (size_t)m->n_cpty, Mz = (size_t)M;
+      const size_t rs = precision == HSIM_FP64 ? sizeof(double) : sizeof(float);
+      return align256(Mz * nc * sizeof(uint32_t)) + align256(Mz * nc * rs) + align256(Mz * n1 * sizeof(double)) +
+             align256(Mz * sizeof(double)) + partial;
+    }
     default:
       return hsim_adjoint_workspace(op, m, g, M, precision);
   }
+}
+
+int hsim_fused(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed, int64_t path_begin,
+               int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths, int precision,
+               int feature_mode, void* features_dev, void* target_dev, double* cva0_dev, void* workspace_dev,
+               size_t ws_bytes, void* stream) {
+  int rc = check_precision(precision);
+  if (rc) return rc;
+  if ((rc = check_market(m))) return rc;
+  if ((rc = check_grid(g))) return rc;
+  if ((rc = check_paths(path_begin, M))) return rc;
+  if ((rc = check_nb(n_b, n_b_per_block, block_paths))) return rc;
+  if (!target_dev || !cva0_dev) return fail(HSIM_EINVAL, "target and cva0 must not be NULL");
+  const size_t rs = precision == HSIM_FP64 ? sizeof(double) : sizeof(float);
+  if (fused_lds_bytes(g->n_dates, m->n_cpty, rs) > kFusedMaxLds)
+    return fail(HSIM_ERANGE, "n_dates x n_cpty too large for the fused kernel's LDS (%zu > %zu bytes): use "
+                "hsim_inner_defaults_cva", fused_lds_bytes(g->n_dates, m->n_cpty, rs), kFusedMaxLds);
+  const size_t need = hsim_workspace_bytes(HSIM_OP_FUSED_LAUNCH, m, g, M, precision);
+  if (!workspace_dev || ws_bytes < need) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, need);
+  const size_t n1 = (size_t)g->n_dates + 1, nc = n1 * (size_t)m->n_cpty, Mz = (size_t)M;
+  char* w = (char*)workspace_dev;
+  FusedArgs f;
+  f.n_b = n_b;
+  f.nb_block = n_b_per_block;
+  f.block_paths = block_paths;
+  f.K = (uint32_t*)w;
+  w += align256(Mz * nc * sizeof(uint32_t));
+  f.Dv = w;
+  w += align256(Mz * nc * rs);
+  f.Iv = (double*)w;
+  w += align256(Mz * n1 * sizeof(double));
+  f.T0 = (double*)w;
+  w += align256(Mz * sizeof(double));
+  double* partial = (double*)w;
+  f.T = target_dev;
+  auto run = [&](auto tag) -> int {
+    using Real = decltype(tag);
+    SimArgs<Real> a;
+    const int r = build_sim_args<Real>(m, p, g, seed, path_begin, M, feature_mode, a);
+    if (r) return r;
+    a.features = (Real*)features_dev;
+    const hipError_t e = launch_fused<Real>(a, f, partial, cva0_dev, (hipStream_t)stream);
+    return e == hipSuccess ? HSIM_OK : device_error(e, "fused simulation launch");
+  };
+  return precision == HSIM_FP32 ? run(0.0f) : run(0.0);
 }
 
 int hsim_inner_defaults_cva(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed,
@@ -688,7 +741,10 @@ int hsim_inner_defaults_cva(const hsim_market* m, const hsim_portfolio* p, const
                             int32_t block_paths, int precision, int feature_mode, void* features_dev,
                             void* target_dev, double* cva0_dev, void* workspace_dev, size_t ws_bytes,
                             void* stream) {
-  int rc = check_precision(precision);
+  // the plain FP32 form differs in the simulation's integrals only; the later stages read them
+  // as FP32 runs do
+  const int stage_precision = precision == HSIM_FP32_PLAIN ? HSIM_FP32 : precision;
+  int rc = check_precision(stage_precision);
   if (rc) return rc;
   if ((rc = check_market(m))) return rc;
   if ((rc = check_grid(g))) return rc;
@@ -698,7 +754,7 @@ int hsim_inner_defaults_cva(const hsim_market* m, const hsim_portfolio* p, const
   const size_t need = hsim_workspace_bytes(HSIM_OP_FUSED, m, g, M, precision);
   if (!workspace_dev || ws_bytes < need) return fail(HSIM_ENOWS, "workspace %zu < %zu bytes", ws_bytes, need);
   const size_t n1 = (size_t)g->n_dates + 1, C = (size_t)m->n_cpty;
-  const size_t rs = precision == HSIM_FP32 ? sizeof(float) : sizeof(double);
+  const size_t rs = precision == HSIM_FP64 ? sizeof(double) : sizeof(float);
   char* w = (char*)workspace_dev;
   double* I = (double*)w;
   w += align256(n1 * M * sizeof(double));
@@ -718,8 +774,8 @@ int hsim_inner_defaults_cva(const hsim_market* m, const hsim_portfolio* p, const
   if ((rc = hsim_inner_defaults(g, m->n_cpty, seed, path_begin, M, n_b, n_b_per_block, block_paths, Lam, cnt,
                                 order, align256(inner_order_bytes(M)), s)))
     return rc;
-  return hsim_targets_cva(g, m->n_cpty, M, n_b, n_b_per_block, block_paths, precision, I, D, cnt, target_dev,
-                          cva0_dev, partial, hsim_workspace_bytes(HSIM_OP_TARGETS, m, g, M, precision), s);
+  return hsim_targets_cva(g, m->n_cpty, M, n_b, n_b_per_block, block_paths, stage_precision, I, D, cnt,
+                          target_dev, cva0_dev, partial, hsim_workspace_bytes(HSIM_OP_TARGETS, m, g, M, precision), s);
 }
 
 }  // extern "C"

@@ -8,6 +8,9 @@
 // E[g g'].  R = E[g g'] - E[g]^2 and Q = E[g^2] - E[g g'] follow on the host.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <limits>
+
 #include "../../include/hsim.h"
 #include "abi_internal.hpp"
 
@@ -73,4 +76,42 @@ extern "C" int hsim_oversim_moments(const hsim_grid* g, int64_t M, int precision
                        (const double*)T2_dev, (const double*)pred_dev, moments_dev);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? HSIM_OK : device_error(e, "pilot moments launch");
+}
+
+extern "C" int hsim_oversim_cost_ratio(double t, double t_prime, double N, double N_prime, double* P_out) {
+  if (!P_out) return fail(HSIM_EINVAL, "P_out is NULL");
+  if (!(t > 0.0) || !(t_prime > 0.0)) return fail(HSIM_EINVAL, "times must be positive");
+  if (N == N_prime || t == t_prime) return fail(HSIM_EINVAL, "the two runs must differ in n_b and in time");
+  const double P = (t_prime * N - t * N_prime) / (t - t_prime);
+  if (!(P > 0.0) || !std::isfinite(P))
+    return fail(HSIM_EINVAL, "timings %.6g s (N=%g) and %.6g s (N'=%g) do not resolve a positive cost ratio", t,
+                N, t_prime, N_prime);
+  *P_out = P;
+  return HSIM_OK;
+}
+
+extern "C" int hsim_oversim_choose(int32_t n_dates1, const double* mom, double P, double Psi, double* R_out,
+                                   double* Q_out, double* Nstar_out, double* N_out, double* M_out) {
+  if (n_dates1 < 1 || !mom || !N_out || !M_out) return fail(HSIM_EINVAL, "bad dates, moments or outputs");
+  if (!(P > 0.0) || !(Psi > 0.0)) return fail(HSIM_EINVAL, "P and Psi must be positive");
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  double sum = 0.0;
+  int defined = 0;
+  for (int i = 0; i < n_dates1; ++i) {
+    const double R = mom[3 * i + 2] - mom[3 * i + 0] * mom[3 * i + 0];
+    const double Q = mom[3 * i + 1] - mom[3 * i + 2];
+    double ns = nan;
+    if (R > 0.0 && Q >= 0.0) {
+      ns = std::sqrt(Q * P / R);
+      sum += ns;
+      ++defined;
+    }
+    if (R_out) R_out[i] = R;
+    if (Q_out) Q_out[i] = Q;
+    if (Nstar_out) Nstar_out[i] = ns;
+  }
+  const double N = defined ? std::fmax(1.0, sum / defined) : 1.0;
+  *N_out = N;
+  *M_out = Psi / (N + P);
+  return defined;
 }

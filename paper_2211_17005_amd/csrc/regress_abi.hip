@@ -7,20 +7,29 @@
 #include "../../include/hsim.h"
 #include "abi_internal.hpp"
 #include "regress.hpp"
+#include "regress_plain.hpp"
 
 using namespace hsim;
 
 namespace {
 
+bool plain(const cva_mlp_cfg* c) { return c->dtype == HSIM_REG_FP32 || c->dtype == HSIM_REG_FP64; }
+size_t elem_bytes(const cva_mlp_cfg* c) { return c->dtype == HSIM_REG_FP64 ? sizeof(double) : sizeof(float); }
+
 int check_cfg(const cva_mlp_cfg* c) {
   if (!c) return fail(HSIM_EINVAL, "cfg is NULL");
-  if (!mlp_supported(c->width, c->hidden))
+  if (c->dtype != HSIM_REG_BF16 && !plain(c)) return fail(HSIM_EINVAL, "unknown regression dtype %d", c->dtype);
+  if (plain(c)) {
+    if (c->width < 1 || c->width > kPlainMaxWidth || c->hidden < 1 || c->hidden > 3)
+      return fail(HSIM_EUNSUPPORTED, "width=%d hidden=%d outside 1..%d x 1..3", c->width, c->hidden, kPlainMaxWidth);
+  } else if (!mlp_supported(c->width, c->hidden)) {
     return fail(HSIM_EUNSUPPORTED, "no kernel built for width=%d hidden=%d", c->width, c->hidden);
+  }
   if (c->d_in < 1 || c->d_in > kMlpDin) return fail(HSIM_ERANGE, "d_in=%d out of [1,%d]", c->d_in, kMlpDin);
   if (c->epochs < 1 || c->batch < 1) return fail(HSIM_EINVAL, "epochs and batch must be >= 1");
   if (c->team < 0 || c->team > 32) return fail(HSIM_ERANGE, "team=%d out of [0,32]", c->team);
-  if (!(c->lr >= 0.0f) || !(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f) ||
-      !(c->eps > 0.0f))
+  if (!(c->lr >= 0.0) || !(c->beta1 >= 0.0 && c->beta1 < 1.0) || !(c->beta2 >= 0.0 && c->beta2 < 1.0) ||
+      !(c->eps > 0.0))
     return fail(HSIM_EINVAL, "bad Adam hyper-parameters");
   return HSIM_OK;
 }
@@ -41,10 +50,10 @@ int fill_args(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int32_t
   a.d_in = c->d_in;
   a.epochs = c->epochs;
   a.batch = c->batch;
-  a.lr = c->lr;
-  a.beta1 = c->beta1;
-  a.beta2 = c->beta2;
-  a.eps = c->eps;
+  a.lr = (float)c->lr;
+  a.beta1 = (float)c->beta1;
+  a.beta2 = (float)c->beta2;
+  a.eps = (float)c->eps;
   a.n_reg = n_reg;
   a.M = M;
   a.n_feat = n_feat;
@@ -141,13 +150,14 @@ int hsim_set_wait_limit(int32_t polls) {
 }
 
 int cva_regress_adam_state(const cva_mlp_cfg* c, int32_t n_reg, int64_t M, const void* workspace_dev, size_t ws_bytes,
-                           float* params_dev, float* m_dev, float* v_dev, void* stream) {
+                           void* params_dev, void* m_dev, void* v_dev, void* stream) {
   if (cva_regress_workspace_bytes(c, n_reg, M) == 0) return fail(HSIM_EINVAL, "bad cfg or n_reg");
   if (!workspace_dev || ws_bytes < cva_regress_workspace_bytes(c, n_reg, M))
     return fail(HSIM_ENOWS, "workspace smaller than the fit's");
-  const size_t bytes = (size_t)MlpLayout{c->width, c->hidden}.n_params() * n_reg * sizeof(float);
-  const float* src = (const float*)workspace_dev;
-  float* dst[3] = {params_dev, m_dev, v_dev};
+  // both paths keep the parameters, then m, then v of every date at the head of the workspace
+  const size_t bytes = (size_t)MlpLayout{c->width, c->hidden}.n_params() * n_reg * elem_bytes(c);
+  const char* src = (const char*)workspace_dev;
+  void* dst[3] = {params_dev, m_dev, v_dev};
   for (int k = 0; k < 3; ++k) {
     if (!dst[k]) continue;
     const hipError_t e = hipMemcpyAsync(dst[k], (const char*)src + k * bytes, bytes, hipMemcpyDeviceToDevice,
@@ -170,20 +180,23 @@ int cva_regress_record_floats(const cva_mlp_cfg* c) {
 }
 
 size_t cva_regress_workspace_bytes(const cva_mlp_cfg* c, int32_t n_reg, int64_t M) {
-  (void)M;
   if (!c || n_reg < 1 || check_cfg(c) != HSIM_OK) return 0;
+  if (plain(c)) return M >= 1 ? plain_workspace_bytes(c, n_reg, M) : 0;
   int G = 0, n_teams = 0;
   if (!choose_team(c, c->warm_start ? 1 : n_reg, G, n_teams)) return 0;
   return reg_ws(c, n_reg, G, n_teams).total;
 }
 
 int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int32_t n_dates_total, int64_t M,
-                    int32_t n_feat, const float* X_dev, const float* Y_dev, const float* W_dev, uint64_t seed,
-                    float* model_dev, float* loss_hist_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
+                    int32_t n_feat, const void* X_dev, const void* Y_dev, const void* W_dev, uint64_t seed,
+                    void* model_dev, void* loss_hist_dev, void* workspace_dev, size_t ws_bytes, void* stream) {
   MlpArgs a;
   int rc = fill_args(c, n_reg, dates, n_dates_total, M, n_feat, a);
   if (rc) return rc;
   if (!X_dev || !Y_dev || !model_dev) return fail(HSIM_EINVAL, "X, Y and model must not be NULL");
+  if (plain(c))
+    return plain_fit(c, n_reg, dates, M, n_feat, X_dev, Y_dev, W_dev, seed, model_dev, loss_hist_dev, workspace_dev,
+                     ws_bytes, (hipStream_t)stream);
   int G = 0, n_teams = 0;
   if (!choose_team(c, c->warm_start ? 1 : n_reg, G, n_teams))
     return fail(HSIM_EDEVICE, "no team of %d workgroups fits on the device", c->team);
@@ -220,11 +233,11 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
     a.losses = (float*)w;
     a.n_blocks = mlp_max_teams(c->width, c->hidden, 1);
   }
-  a.X = X_dev;
-  a.Y = Y_dev;
-  a.Wt = W_dev;
-  a.model = model_dev;
-  a.loss_hist = loss_hist_dev;
+  a.X = (const float*)X_dev;
+  a.Y = (const float*)Y_dev;
+  a.Wt = (const float*)W_dev;
+  a.model = (float*)model_dev;
+  a.loss_hist = (float*)loss_hist_dev;
   a.key0 = (uint32_t)seed;
   a.key1 = (uint32_t)(seed >> 32);
   hipStream_t s = (hipStream_t)stream;
@@ -262,16 +275,17 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
 }
 
 int cva_regress_predict(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int32_t n_dates_total, int64_t M,
-                        int32_t n_feat, const float* X_dev, const float* model_dev, float* out_dev, void* stream) {
+                        int32_t n_feat, const void* X_dev, const void* model_dev, void* out_dev, void* stream) {
   MlpArgs a;
   int rc = fill_args(c, n_reg, dates, n_dates_total, M, n_feat, a);
   if (rc) return rc;
   if (!X_dev || !model_dev || !out_dev) return fail(HSIM_EINVAL, "X, model and out must not be NULL");
-  a.X = X_dev;
+  if (plain(c)) return plain_predict(c, n_reg, dates, M, n_feat, X_dev, model_dev, out_dev, (hipStream_t)stream);
+  a.X = (const float*)X_dev;
   a.Y = nullptr;
   a.Wt = nullptr;
   a.model = (float*)model_dev;
-  hipError_t e = launch_mlp_predict(a, out_dev, (hipStream_t)stream);
+  hipError_t e = launch_mlp_predict(a, (float*)out_dev, (hipStream_t)stream);
   return e == hipSuccess ? HSIM_OK : device_error(e, "prediction launch");
 }
 

@@ -21,6 +21,8 @@
 // indices, so they come through the scalar cache.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "philox.hpp"
 #include "sim.hpp"
 
@@ -31,15 +33,16 @@ __device__ __forceinline__ double exp_r(double x) { return exp(x); }
 __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 
-template <typename Real, int NE, int NC>
+// Acc: type of the discount and intensity integrals (double; float in the plain FP32 form).
+template <typename Real, int NE, int NC, typename Acc = double>
 struct OuterState {
   Real r[NE];
   Real x[NE > 1 ? NE - 1 : 1];
   Real g[NC];
   Real gcomp[NC];          // rounding error carried by the compensated intensity update
   Real invzc[NE];          // 1 / ZC^e_{t-}(t-+delta), from r^e at the last reset date
-  double I;
-  double Lam[NC];
+  Acc I;
+  Acc Lam[NC];
 };
 
 // 1 / ZC^e_t(t + delta) from r^e at a reset date: the next floating coupon's discount.
@@ -51,16 +54,16 @@ __device__ __forceinline__ Real reset_inv_zc(const SimArgs<Real>& a, int e, Real
 }
 
 // The reset bookkeeping of pricing date i without the pricing itself.
-template <typename Real, int NE, int NC>
-__device__ __forceinline__ void reset_only(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st, int i) {
+template <typename Real, int NE, int NC, typename Acc = double>
+__device__ __forceinline__ void reset_only(const SimArgs<Real>& a, OuterState<Real, NE, NC, Acc>& st, int i) {
   if ((i % a.q) != 0) return;
 #pragma unroll
   for (int e = 0; e < NE; ++e) st.invzc[e] = reset_inv_zc<Real, NE, NC>(a, e, st.r[e]);
 }
 
 // Value of the book per counterparty at pricing date i (updates the reset state).
-template <typename Real, int NE, int NC>
-__device__ __forceinline__ void price(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st, int i,
+template <typename Real, int NE, int NC, typename Acc = double>
+__device__ __forceinline__ void price(const SimArgs<Real>& a, OuterState<Real, NE, NC, Acc>& st, int i,
                                       Real mtm[NC]) {
   const int n = a.n_dates;
   const int q = a.q;
@@ -112,43 +115,57 @@ __device__ __forceinline__ void price(const SimArgs<Real>& a, OuterState<Real, N
 }
 
 // Price the book and emit every per-date output at date i.
-template <typename Real, int NE, int NC>
-__device__ __forceinline__ void price_and_emit(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st,
-                                               int i, int64_t kl) {
+// Exposure D^c = LGD_c beta (MtM^c)^+ of one counterparty.
+template <typename Real, typename Acc>
+__device__ __forceinline__ Real exposure(const SimArgs<Real>& a, Acc beta, Real mtm, int c) {
+  const Real pos = mtm > (Real)0 ? mtm : (Real)0;
+  return (Real)((Acc)a.lgd[c] * beta * (Acc)pos);
+}
+
+// Regression features of date i (date-major rows, one column per lane).
+template <typename Real, int NE, int NC, typename Acc>
+__device__ __forceinline__ void emit_features(const SimArgs<Real>& a, const OuterState<Real, NE, NC, Acc>& st,
+                                              int i, int64_t kl) {
+  if (!a.features) return;
   const int64_t M = a.M;
-  Real mtm[NC];
-  price<Real, NE, NC>(a, st, i, mtm);
-  const double beta = exp(-st.I);
-  a.I[(int64_t)i * M + kl] = st.I;
+  Real* f = a.features + (int64_t)i * a.n_feat * M + kl;
+  int col = 0;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const int64_t o = ((int64_t)i * NC + c) * M + kl;
-    a.Lam[o] = st.Lam[c];
-    const Real pos = mtm[c] > (Real)0 ? mtm[c] : (Real)0;
-    a.D[o] = (Real)((double)a.lgd[c] * beta * (double)pos);
-    if (a.MtM) a.MtM[o] = mtm[c];
-  }
-  if (a.features) {
-    Real* f = a.features + (int64_t)i * a.n_feat * M + kl;
-    int col = 0;
+  for (int e = 0; e < NE; ++e) f[(int64_t)(col++) * M] = st.r[e];
 #pragma unroll
-    for (int e = 0; e < NE; ++e) f[(int64_t)(col++) * M] = st.r[e];
+  for (int e = 1; e < NE; ++e) f[(int64_t)(col++) * M] = st.x[e - 1];
 #pragma unroll
-    for (int e = 1; e < NE; ++e) f[(int64_t)(col++) * M] = st.x[e - 1];
+  for (int c = 0; c < NC; ++c) f[(int64_t)(col++) * M] = st.g[c];
+  if (a.feature_mode == 1) {
+    Acc sl = 0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) f[(int64_t)(col++) * M] = st.g[c];
-    if (a.feature_mode == 1) {
-      double sl = 0.0;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) sl += st.Lam[c];
-      f[(int64_t)(col++) * M] = (Real)st.I;
-      f[(int64_t)(col++) * M] = (Real)sl;
-    }
+    for (int c = 0; c < NC; ++c) sl += st.Lam[c];
+    f[(int64_t)(col++) * M] = (Real)st.I;
+    f[(int64_t)(col++) * M] = (Real)sl;
   }
 }
 
-template <typename Real, int NE, int NC>
-__device__ __forceinline__ void init_state(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st) {
+// Price the book and emit every per-date output at date i.
+template <typename Real, int NE, int NC, typename Acc = double>
+__device__ __forceinline__ void price_and_emit(const SimArgs<Real>& a, OuterState<Real, NE, NC, Acc>& st,
+                                               int i, int64_t kl) {
+  const int64_t M = a.M;
+  Real mtm[NC];
+  price<Real, NE, NC, Acc>(a, st, i, mtm);
+  const Acc beta = exp_r(-st.I);
+  a.I[(int64_t)i * M + kl] = (double)st.I;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t o = ((int64_t)i * NC + c) * M + kl;
+    a.Lam[o] = (double)st.Lam[c];
+    a.D[o] = exposure<Real, Acc>(a, beta, mtm[c], c);
+    if (a.MtM) a.MtM[o] = mtm[c];
+  }
+  emit_features<Real, NE, NC, Acc>(a, st, i, kl);
+}
+
+template <typename Real, int NE, int NC, typename Acc = double>
+__device__ __forceinline__ void init_state(const SimArgs<Real>& a, OuterState<Real, NE, NC, Acc>& st) {
 #pragma unroll
   for (int e = 0; e < NE; ++e) st.r[e] = a.r0[e];
 #pragma unroll
@@ -157,15 +174,15 @@ __device__ __forceinline__ void init_state(const SimArgs<Real>& a, OuterState<Re
   for (int c = 0; c < NC; ++c) {
     st.g[c] = a.g0[c];
     st.gcomp[c] = (Real)0;
-    st.Lam[c] = 0.0;
+    st.Lam[c] = 0;
   }
-  st.I = 0.0;
+  st.I = 0;
 }
 
 // The n_sub Euler sub-steps from t_i to t_{i+1}, normals from the Philox counters
 // (k, s, c2 + (f >> 2), tag).
-template <typename Real, int NE, int NC>
-__device__ __forceinline__ void advance(const SimArgs<Real>& a, OuterState<Real, NE, NC>& st, int i,
+template <typename Real, int NE, int NC, typename Acc = double>
+__device__ __forceinline__ void advance(const SimArgs<Real>& a, OuterState<Real, NE, NC, Acc>& st, int i,
                                         uint32_t k, uint32_t c2, uint32_t tag) {
   constexpr int DW = 2 * NE - 1;
   constexpr int NZ = DW + NC;
@@ -178,7 +195,7 @@ __device__ __forceinline__ void advance(const SimArgs<Real>& a, OuterState<Real,
     using CL = CoefLayout<NE, NC>;
     const Real* cf = a.coef;
     const Real dt = a.dt;
-    const double hdt = a.half_dt;
+    const Acc hdt = (Acc)a.half_dt;
     const uint32_t s = (uint32_t)(i * a.n_sub + j);
     // Normals arrive four at a time; each market normal z_f is folded at once into the
     // correlated increments W_p += L_{pf} z_f (p >= f), each CIR normal drives its
@@ -207,7 +224,7 @@ __device__ __forceinline__ void advance(const SimArgs<Real>& a, OuterState<Real,
           st.gcomp[c] = inc - (gs - st.g[c]);
           st.g[c] = gs;
           const Real gn = st.g[c] > (Real)0 ? st.g[c] : (Real)0;
-          st.Lam[c] += hdt * ((double)gp + (double)gn);
+          st.Lam[c] += hdt * ((Acc)gp + (Acc)gn);
         }
       }
     }
@@ -218,22 +235,22 @@ __device__ __forceinline__ void advance(const SimArgs<Real>& a, OuterState<Real,
 #pragma unroll
     for (int e = 0; e < NE; ++e)
       st.r[e] = st.r[e] + cf[CL::r_adt + e] * (cf[CL::r_lvl + e] - st.r[e]) + cf[CL::r_vol + e] * W[e];
-    st.I += hdt * ((double)r0old + (double)st.r[0]);
+    st.I += hdt * ((Acc)r0old + (Acc)st.r[0]);
   }
 }
 
-template <typename Real, int NE, int NC>
+template <typename Real, int NE, int NC, typename Acc>
 __global__ __launch_bounds__(kOuterBlock) __attribute__((amdgpu_waves_per_eu(NE > 4 ? 2 : 4)))
 void outer_kernel(const SimArgs<Real> a) {
   const int64_t kl = (int64_t)blockIdx.x * kOuterBlock + threadIdx.x;
   if (kl >= a.M) return;
   const uint32_t k = a.path_begin + (uint32_t)kl;
-  OuterState<Real, NE, NC> st;
-  init_state<Real, NE, NC>(a, st);
-  price_and_emit<Real, NE, NC>(a, st, 0, kl);
+  OuterState<Real, NE, NC, Acc> st;
+  init_state<Real, NE, NC, Acc>(a, st);
+  price_and_emit<Real, NE, NC, Acc>(a, st, 0, kl);
   for (int i = 0; i < a.n_dates; ++i) {
-    advance<Real, NE, NC>(a, st, i, k, 0u, kTagOuter);
-    price_and_emit<Real, NE, NC>(a, st, i + 1, kl);
+    advance<Real, NE, NC, Acc>(a, st, i, k, 0u, kTagOuter);
+    price_and_emit<Real, NE, NC, Acc>(a, st, i + 1, kl);
   }
 }
 
@@ -486,6 +503,13 @@ __global__ __launch_bounds__(1024) void inner_order_kernel(const int32_t* nb_blo
 // A_i = n_b - (defaults up to t_i) = n_b - total + (defaults after t_i).
 enum TargetMode { kNested = 0, kIntensity = 1, kAlive = 2 };
 
+// One term of a date's part of the suffix sum: H + D^c_j w^c_j in FP64 (shared by the fused
+// kernel so that both forms round identically).
+template <typename Real>
+__device__ __forceinline__ double date_term(double H, Real D, double w) {
+  return __builtin_fma((double)D, w, H);
+}
+
 template <typename Real, int kMode>
 __global__ __launch_bounds__(kTargetBlock) void targets_kernel(const TargetArgs<Real> a) {
   __shared__ double red[kTargetBlock];
@@ -507,6 +531,7 @@ __global__ __launch_bounds__(kTargetBlock) void targets_kernel(const TargetArgs<
     }
     a.T[(int64_t)n * M + kl] = (Real)0;
     for (int i = n - 1; i >= 0; --i) {
+      double Hj = 0.0;                     // this date's terms, summed over c in order
       for (int c = 0; c < C; ++c) {
         const int64_t o = ((int64_t)(i + 1) * C + c) * M + kl;
         double wgt;
@@ -515,8 +540,9 @@ __global__ __launch_bounds__(kTargetBlock) void targets_kernel(const TargetArgs<
         } else {
           wgt = (double)a.counts[o];
         }
-        S += (double)a.D[o] * wgt;
+        Hj = date_term(Hj, a.D[o], wgt);
       }
+      S += Hj;
       double Ti;
       if constexpr (kMode == kAlive) {
         later += a.counts[(int64_t)(i + 1) * M + kl];
@@ -551,6 +577,142 @@ __global__ __launch_bounds__(kTargetBlock) void reduce_partials(const double* pa
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0] * inv_M;
+}
+
+// ------------------------------------------------------------------------------------
+// fused simulation: outer paths, inner draws and targets in one launch
+// ------------------------------------------------------------------------------------
+// One workgroup (one wave) per tile of 64 outer paths.  Phase 1 is outer_kernel's simulation,
+// one lane per path; at every pricing date a lane writes its features (as outer_kernel) and, into
+// a path-major table in the workspace, what the inner draws and the targets need: the integer
+// default threshold of every counterparty (the rule Lambda_j >= -log u on the 23-bit uniforms),
+// the exposures D^c_j and the discount integral I_j.  Phase 2 takes the tile's paths one at a
+// time: the wave stages the path's table (contiguous, just written by this workgroup) in LDS and
+// draws its n_b x C inner defaults cooperatively (lanes = Philox calls of four draws), locating
+// each default date by the same binary search as inner_kernel and counting it in an LDS
+// histogram; lanes then form the per-date terms sum_c D^c_j counts^c_j, one lane the suffix sums
+// over dates, and lanes the targets T_i.  The order of every floating-point operation is that of
+// targets_kernel, so targets and CVA_0 equal the separate stages' bit for bit.
+template <typename Real, int NE, int NC>
+__device__ __forceinline__ void fused_emit(const SimArgs<Real>& a, const FusedArgs& f,
+                                           OuterState<Real, NE, NC, double>& st, int i, int64_t kl) {
+  const int n1 = a.n_dates + 1;
+  Real mtm[NC];
+  price<Real, NE, NC, double>(a, st, i, mtm);
+  const double beta = exp(-st.I);
+  const int64_t row = (kl * n1 + i) * NC;
+  Real* Dv = (Real*)f.Dv;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    f.K[row + c] = default_threshold(st.Lam[c]);
+    Dv[row + c] = exposure<Real, double>(a, beta, mtm[c], c);
+  }
+  f.Iv[kl * n1 + i] = st.I;
+  emit_features<Real, NE, NC, double>(a, st, i, kl);
+}
+
+template <typename Real>
+__device__ void fused_inner_targets(const SimArgs<Real>& a, const FusedArgs& f, int64_t tile, char* lds) {
+  const int lane = threadIdx.x, n = a.n_dates, C = a.n_cpty, n1 = n + 1;
+  const int64_t M = a.M;
+  const int nc = n1 * C;
+  uint32_t* Kl = (uint32_t*)lds;                          // [n1][C] thresholds
+  uint32_t* hist = Kl + nc;                               // [n1][C] defaults per date
+  double* Il = (double*)(lds + fused_lds_offset_f64(n, C)); // [n1] I_j
+  double* Hs = Il + n1;                                   // [n1] date terms, then suffix sums
+  Real* Dl = (Real*)(Hs + n1);                            // [n1][C] exposures
+  const Real* Dv = (const Real*)f.Dv;
+  Real* T = (Real*)f.T;
+  const int nb = f.nb_block ? f.nb_block[(tile * kOuterBlock) / f.block_paths] : f.n_b;
+  const double inv_nb = 1.0 / (double)nb;
+  const int calls = (nb + 3) / 4;
+  const int64_t first = tile * kOuterBlock;
+  const int count = (int)min((int64_t)kOuterBlock, M - first);
+  for (int p = 0; p < count; ++p) {
+    const int64_t kl = first + p;
+    const uint32_t k = a.path_begin + (uint32_t)kl;
+    for (int e = lane; e < nc; e += kOuterBlock) {
+      Kl[e] = f.K[kl * nc + e];
+      Dl[e] = Dv[kl * nc + e];
+      hist[e] = 0u;
+    }
+    for (int e = lane; e < n1; e += kOuterBlock) Il[e] = f.Iv[kl * n1 + e];
+    __syncthreads();
+    for (int q = lane; q < C * calls; q += kOuterBlock) {
+      const int c = q / calls, l4 = 4 * (q - c * calls);
+      const uint32_t Kn = Kl[n * C + c];
+      const u32x4 w = philox4x32_10(k, (uint32_t)(l4 >> 2), (uint32_t)c, kTagInner, a.key0, a.key1);
+      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (l4 + t >= nb) break;
+        const uint32_t m = grid23(ws[t]);
+        if (m >= Kn) {                       // defaults by the horizon: smallest j with K_j <= m
+          int lo = 1, hi = n;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (m >= Kl[mid * C + c]) hi = mid; else lo = mid + 1;
+          }
+          atomicAdd(&hist[lo * C + c], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = 1 + lane; j <= n; j += kOuterBlock) {
+      double H = 0.0;
+      for (int c = 0; c < C; ++c) H = date_term(H, Dl[j * C + c], (double)hist[j * C + c]);
+      Hs[j] = H;
+    }
+    __syncthreads();
+    if (lane == 0) {                         // S_i = sum_{j > i} H_j, added from the last date down
+      double S = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        S += Hs[i + 1];
+        Hs[i + 1] = S;
+      }
+    }
+    __syncthreads();
+    for (int i = lane; i <= n; i += kOuterBlock) {
+      const double Ti = i == n ? 0.0 : Hs[i + 1] * exp(Il[i]) * inv_nb;
+      T[(int64_t)i * M + kl] = (Real)Ti;
+      if (i == 0) f.T0[kl] = Ti;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename Real, int NE, int NC>
+__global__ __launch_bounds__(kOuterBlock) __attribute__((amdgpu_waves_per_eu(NE > 4 ? 2 : 4)))
+void fused_kernel(const SimArgs<Real> a, const FusedArgs f) {
+  extern __shared__ __attribute__((aligned(16))) char fused_lds[];
+  const int64_t tile = blockIdx.x;
+  const int64_t kl = tile * kOuterBlock + threadIdx.x;
+  if (kl < a.M) {
+    const uint32_t k = a.path_begin + (uint32_t)kl;
+    OuterState<Real, NE, NC, double> st;
+    init_state<Real, NE, NC, double>(a, st);
+    fused_emit<Real, NE, NC>(a, f, st, 0, kl);
+    for (int i = 0; i < a.n_dates; ++i) {
+      advance<Real, NE, NC, double>(a, st, i, k, 0u, kTagOuter);
+      fused_emit<Real, NE, NC>(a, f, st, i + 1, kl);
+    }
+  }
+  __threadfence_block();
+  __syncthreads();                           // the tile's table is complete and visible
+  fused_inner_targets<Real>(a, f, tile, fused_lds);
+}
+
+// FP64 block partials of CVA_0 from the T_0 values of the fused kernel, in targets_kernel's order.
+__global__ __launch_bounds__(kTargetBlock) void cva0_partials_kernel(int64_t M, const double* T0, double* partial) {
+  __shared__ double red[kTargetBlock];
+  const int64_t kl = (int64_t)blockIdx.x * kTargetBlock + threadIdx.x;
+  red[threadIdx.x] = kl < M ? T0[kl] : 0.0;
+  __syncthreads();
+  for (int w = kTargetBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 // ------------------------------------------------------------------------------------
@@ -593,17 +755,51 @@ bool outer_supported(int n_ccy, int n_cpty) {
 }
 
 template <typename Real>
-hipError_t launch_outer(const SimArgs<Real>& a, hipStream_t stream) {
+hipError_t launch_outer(const SimArgs<Real>& a, hipStream_t stream, bool fp32_integrals) {
   const dim3 grid((unsigned)((a.M + kOuterBlock - 1) / kOuterBlock));
+  if constexpr (std::is_same<Real, float>::value) {
+    if (fp32_integrals) {
+#define X(ne, nc)                                                                                  \
+      if (a.n_ccy == ne && a.n_cpty == nc) {                                                       \
+        hipLaunchKernelGGL((outer_kernel<float, ne, nc, float>), grid, dim3(kOuterBlock), 0, stream, a); \
+        return hipGetLastError();                                                                  \
+      }
+      HSIM_SHAPES(X)
+#undef X
+      return hipErrorInvalidValue;
+    }
+  }
 #define X(ne, nc)                                                                   \
   if (a.n_ccy == ne && a.n_cpty == nc) {                                            \
-    hipLaunchKernelGGL((outer_kernel<Real, ne, nc>), grid, dim3(kOuterBlock), 0, stream, a); \
+    hipLaunchKernelGGL((outer_kernel<Real, ne, nc, double>), grid, dim3(kOuterBlock), 0, stream, a); \
     return hipGetLastError();                                                       \
   }
   HSIM_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
+
+template <typename Real>
+hipError_t launch_fused(const SimArgs<Real>& a, const FusedArgs& f, double* partial, double* cva0, hipStream_t stream) {
+  const int64_t tiles = (a.M + kOuterBlock - 1) / kOuterBlock;
+  const size_t lds = fused_lds_bytes(a.n_dates, a.n_cpty, sizeof(Real));
+  hipError_t e = hipErrorInvalidValue;
+#define X(ne, nc)                                                                                   \
+  if (a.n_ccy == ne && a.n_cpty == nc) {                                                            \
+    hipLaunchKernelGGL((fused_kernel<Real, ne, nc>), dim3((unsigned)tiles), dim3(kOuterBlock), lds, stream, a, f); \
+    e = hipGetLastError();                                                                          \
+  }
+  HSIM_SHAPES(X)
+#undef X
+  if (e != hipSuccess) return e;
+  const int64_t nblk = (a.M + kTargetBlock - 1) / kTargetBlock;
+  hipLaunchKernelGGL(cva0_partials_kernel, dim3((unsigned)nblk), dim3(kTargetBlock), 0, stream, a.M, f.T0, partial);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kTargetBlock), 0, stream, partial, nblk, 1.0 / (double)a.M, cva0);
+  return hipGetLastError();
+}
+template hipError_t launch_fused<float>(const SimArgs<float>&, const FusedArgs&, double*, double*, hipStream_t);
+template hipError_t launch_fused<double>(const SimArgs<double>&, const FusedArgs&, double*, double*, hipStream_t);
 
 size_t inner_order_bytes(int64_t M) { return (size_t)((M + kInnerBlock - 1) / kInnerBlock + 1) * sizeof(int32_t); }
 
@@ -704,8 +900,8 @@ hipError_t launch_normals_fill(uint64_t seed, int64_t path_begin, int64_t count,
   return hipGetLastError();
 }
 
-template hipError_t launch_outer<float>(const SimArgs<float>&, hipStream_t);
-template hipError_t launch_outer<double>(const SimArgs<double>&, hipStream_t);
+template hipError_t launch_outer<float>(const SimArgs<float>&, hipStream_t, bool);
+template hipError_t launch_outer<double>(const SimArgs<double>&, hipStream_t, bool);
 template hipError_t launch_branch<float>(const SimArgs<float>&, const BranchArgs&, hipStream_t);
 template hipError_t launch_branch<double>(const SimArgs<double>&, const BranchArgs&, hipStream_t);
 template hipError_t launch_targets<float>(const TargetArgs<float>&, hipStream_t);

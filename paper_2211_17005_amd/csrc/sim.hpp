@@ -104,6 +104,29 @@ struct BranchArgs {
 };
 constexpr int kBranchStats = 6;      // nu, nu^2, U, (phi - nu)^2, phi^2 - 2 phi nu + U, phi
 
+// Fused simulation (hsim_fused): the per-path tables of the inner stage, path-major in the
+// workspace, and the outputs.
+struct FusedArgs {
+  int32_t n_b;                       // uniform n_b when nb_block is null
+  const int32_t* nb_block;           // device [ceil(M/block_paths)] or null
+  int32_t block_paths;               // a multiple of 64
+  uint32_t* K;                       // [M][n+1][C] default thresholds
+  void* Dv;                          // [M][n+1][C] exposures (Real)
+  double* Iv;                        // [M][n+1] discount integrals
+  void* T;                           // [n+1][M] targets (Real)
+  double* T0;                        // [M] T_0 in FP64 (the CVA_0 reduction's input)
+};
+
+// LDS of one fused workgroup: thresholds and histogram [n+1][C] uint32 each, then (8-byte
+// aligned) I and the date terms [n+1] double each, then the exposures [n+1][C].
+__host__ __device__ inline size_t fused_lds_offset_f64(int n, int C) {
+  return ((size_t)2 * (n + 1) * C * 4 + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t fused_lds_bytes(int n, int C, size_t real_bytes) {
+  return fused_lds_offset_f64(n, C) + (size_t)2 * (n + 1) * 8 + (size_t)(n + 1) * C * real_bytes;
+}
+constexpr size_t kFusedMaxLds = 64 * 1024;   // beyond: the separate stages (occupancy of the outer phase)
+
 // offsets into SimArgs::coef
 template <int NE, int NC>
 struct CoefLayout {
@@ -121,13 +144,18 @@ constexpr int kTargetBlock = 256;
 // Launchers; return hipSuccess or the launch error.  `supported` reports whether a
 // (n_ccy, n_cpty) pair has a compiled instantiation.
 bool outer_supported(int n_ccy, int n_cpty);
+// fp32_integrals (Real = float only): the discount and intensity integrals accumulate in FP32
+// (the plain form) instead of FP64.
 template <typename Real>
-hipError_t launch_outer(const SimArgs<Real>& a, hipStream_t stream);
+hipError_t launch_outer(const SimArgs<Real>& a, hipStream_t stream, bool fp32_integrals = false);
 hipError_t launch_inner(const InnerArgs& a, hipStream_t stream);
 // Workspace of the longest-first schedule of an uneven-n_b inner launch over M paths.
 size_t inner_order_bytes(int64_t M);
 template <typename Real>
 hipError_t launch_targets(const TargetArgs<Real>& a, hipStream_t stream);
+// Fused simulation, then the CVA_0 reduction of f.T0 (partial: ceil(M / kTargetBlock) doubles).
+template <typename Real>
+hipError_t launch_fused(const SimArgs<Real>& a, const FusedArgs& f, double* partial, double* cva0, hipStream_t stream);
 template <typename Real>
 hipError_t launch_branch(const SimArgs<Real>& a, const BranchArgs& b, hipStream_t stream);
 template <typename Real>

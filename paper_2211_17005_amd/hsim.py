@@ -17,9 +17,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhsim.so")
 
-HSIM_FP64, HSIM_FP32 = 0, 1
+HSIM_FP64, HSIM_FP32, HSIM_FP32_PLAIN = 0, 1, 2
+REG_BF16, REG_FP32, REG_FP64 = 0, 1, 2
 FEAT_FACTORS, FEAT_FACTORS_PLUS = 0, 1
-OP_INNER, OP_TARGETS, OP_FUSED, OP_ADJOINT, OP_BRANCH = 1, 2, 3, 4, 5
+OP_INNER, OP_TARGETS, OP_FUSED, OP_ADJOINT, OP_BRANCH, OP_FUSED_LAUNCH = 1, 2, 3, 4, 5, 6
 HSIM_EINVAL, HSIM_ERANGE, HSIM_ENOWS, HSIM_EDEVICE, HSIM_EUNSUPPORTED, HSIM_ETIMEOUT = -1, -2, -3, -4, -5, -6
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -48,10 +49,10 @@ class Portfolio(ctypes.Structure):
 
 class MlpCfg(ctypes.Structure):
     _fields_ = [("hidden", ctypes.c_int32), ("width", ctypes.c_int32), ("d_in", ctypes.c_int32),
-                ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
-                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
                 ("warm_start", ctypes.c_int32), ("init_tag", ctypes.c_int32),
-                ("team", ctypes.c_int32)]
+                ("team", ctypes.c_int32), ("dtype", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -94,6 +95,8 @@ def lib():
                                                    ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, sz,
                                                    vp]),
         "hsim_workspace_bytes": (sz, [ctypes.c_int, M_, G_, i64, ctypes.c_int]),
+        "hsim_fused": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i32, vp, i32, ctypes.c_int, ctypes.c_int,
+                                      vp, vp, vp, vp, sz, vp]),
         "hsim_n_params": (ctypes.c_int, [M_]),
         "cva_adjoint": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, vp, vp, vp, sz, vp]),
         "cva_regress_record_floats": (ctypes.c_int, [ctypes.POINTER(MlpCfg)]),
@@ -114,6 +117,10 @@ def lib():
                                                vp, vp, sz, vp]),
         "cva_regress_adam_state": (ctypes.c_int, [ctypes.POINTER(MlpCfg), i32, i64, vp, sz, vp, vp, vp, vp]),
         "hsim_set_wait_limit": (ctypes.c_int, [i32]),
+        "hsim_oversim_cost_ratio": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                   ctypes.c_double, _c_f64p]),
+        "hsim_oversim_choose": (ctypes.c_int, [i32, _c_f64p, ctypes.c_double, ctypes.c_double, _c_f64p,
+                                               _c_f64p, _c_f64p, _c_f64p, _c_f64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -200,7 +207,7 @@ def _expect(t, dtype, shape, name):
 
 def _real(precision):
     import torch
-    return torch.float32 if precision == HSIM_FP32 else torch.float64
+    return torch.float64 if precision == HSIM_FP64 else torch.float32
 
 
 # ------------------------------------------------------------------------------- entry points
@@ -455,6 +462,27 @@ def oversim_moments(grid, T1, T2, pred=None, precision: int = HSIM_FP32):
     return out
 
 
+def oversim_cost_ratio(t: float, t_prime: float, N: float, N_prime: float) -> float:
+    """hsim_oversim_cost_ratio: P from two timings (l:ratio)."""
+    P = ctypes.c_double(0.0)
+    check(lib().hsim_oversim_cost_ratio(float(t), float(t_prime), float(N), float(N_prime), ctypes.byref(P)))
+    return P.value
+
+
+def oversim_choose(moments, P: float, Psi: float) -> dict:
+    """hsim_oversim_choose on host moments [n+1][3]: R, Q, N*_i (NaN where undefined), N, M."""
+    mom = np.ascontiguousarray(np.asarray(moments, dtype=np.float64))
+    n1 = int(mom.shape[0])
+    R, Q, Ns = np.empty(n1), np.empty(n1), np.empty(n1)
+    N, Mo = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().hsim_oversim_choose(n1, mom.ctypes.data_as(_c_f64p), float(P), float(Psi),
+                                   R.ctypes.data_as(_c_f64p), Q.ctypes.data_as(_c_f64p),
+                                   Ns.ctypes.data_as(_c_f64p), ctypes.byref(N), ctypes.byref(Mo))
+    if rc < 0:
+        check(rc)
+    return {"R": R, "Q": Q, "N_dates": Ns, "N": N.value, "M": Mo.value, "defined": rc}
+
+
 def workspace_bytes(op: int, w, M: int, precision: int) -> int:
     km = market_struct(w.market)
     g = grid_struct(w.grid)
@@ -497,6 +525,26 @@ class Solver:
         return self.features, self.T, self.cva0
 
 
+class FusedSolver(Solver):
+    """hsim_fused: the whole simulation in one launch (same outputs as Solver.inner_defaults_cva)."""
+
+    def __init__(self, w, precision: int = HSIM_FP32, M: Optional[int] = None, fixed=None,
+                 n_b_per_block=None, block_paths: int = 64, market=None):
+        import torch
+        super().__init__(w, precision, M, fixed, n_b_per_block, block_paths, market)
+        self.wsb = lib().hsim_workspace_bytes(OP_FUSED_LAUNCH, ctypes.byref(self.km.struct),
+                                              ctypes.byref(self.g), self.M, precision)
+        self.ws = torch.empty(self.wsb, dtype=torch.uint8, device="cuda")
+
+    def run(self, path_begin: int = 0, want_features: bool = True):
+        check(lib().hsim_fused(
+            ctypes.byref(self.km.struct), ctypes.byref(self.kp.struct), ctypes.byref(self.g),
+            self.w.seed, path_begin, self.M, self.nb, _dptr(self.nbt), self.bp, self.precision,
+            self.fm, _dptr(self.features if want_features else None), _dptr(self.T),
+            _dptr(self.cva0), _dptr(self.ws), self.wsb, _stream()))
+        return self.features, self.T, self.cva0
+
+
 def inner_defaults_cva(w, precision: int = HSIM_FP32, path_begin: int = 0, M=None,
                        n_b_per_block=None, block_paths: int = 64):
     s = Solver(w, precision, M, n_b_per_block=n_b_per_block, block_paths=block_paths)
@@ -505,13 +553,19 @@ def inner_defaults_cva(w, precision: int = HSIM_FP32, path_begin: int = 0, M=Non
 
 # ------------------------------------------------------------------------------- regression
 def mlp_cfg(mlp, d_in: int, M: int, warm_start: bool = False, init_tag: int = 0,
-            team: int = 0) -> MlpCfg:
+            team: int = 0, dtype: int = REG_BF16) -> MlpCfg:
     """C config from a workload's MLP settings (batch = M / n_batches when no batch is given);
-    team = workgroups per date (0: the library's choice)."""
+    team = workgroups per date (0: the library's choice); dtype REG_BF16 / REG_FP32 / REG_FP64."""
     batch = int(mlp.batch) if getattr(mlp, "batch", None) else max(1, M // int(mlp.n_batches))
     return MlpCfg(int(mlp.hidden), int(mlp.width), int(d_in), int(mlp.epochs), batch,
                   float(mlp.lr), float(mlp.beta1), float(mlp.beta2), float(mlp.eps),
-                  1 if warm_start else 0, int(init_tag), int(team))
+                  1 if warm_start else 0, int(init_tag), int(team), int(dtype))
+
+
+def reg_dtype(cfg: MlpCfg):
+    """torch element type of a fit's inputs, model and losses."""
+    import torch
+    return torch.float64 if cfg.dtype == REG_FP64 else torch.float32
 
 
 def record_floats(cfg: MlpCfg) -> int:
@@ -522,19 +576,20 @@ def record_floats(cfg: MlpCfg) -> int:
 
 
 def regress_fit(cfg: MlpCfg, dates, X, Y, seed: int = 0, want_loss: bool = True, W=None):
-    """cva_regress_fit: X [n+1][n_feat][M] float32, Y [n+1][M] float32, W [n+1][M] float32 row
-    weights or None (device)."""
+    """cva_regress_fit: X [n+1][n_feat][M], Y [n+1][M], W [n+1][M] row weights or None (device;
+    float32, or float64 for REG_FP64)."""
     import torch
     n1, n_feat, M = X.shape
-    _expect(Y, torch.float32, (n1, M), "Y")
-    _expect(X, torch.float32, (n1, n_feat, M), "X")
+    R = reg_dtype(cfg)
+    _expect(Y, R, (n1, M), "Y")
+    _expect(X, R, (n1, n_feat, M), "X")
     if W is not None:
-        _expect(W, torch.float32, (n1, M), "W")
+        _expect(W, R, (n1, M), "W")
     d = _i32(dates)
     n_reg = int(d.size)
     rec = record_floats(cfg)
-    model = torch.zeros((n_reg, rec), dtype=torch.float32, device="cuda")
-    loss = torch.zeros((n_reg, cfg.epochs), dtype=torch.float32, device="cuda") if want_loss else None
+    model = torch.zeros((n_reg, rec), dtype=R, device="cuda")
+    loss = torch.zeros((n_reg, cfg.epochs), dtype=R, device="cuda") if want_loss else None
     wsb = lib().cva_regress_workspace_bytes(ctypes.byref(cfg), n_reg, M)
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     check(lib().cva_regress_fit(ctypes.byref(cfg), n_reg, d.ctypes.data_as(_c_i32p), n1, M, n_feat,
@@ -550,7 +605,7 @@ def regress_adam_state(cfg: MlpCfg, n_reg: int, M: int, ws):
     npar = L.cva_regress_param_floats(ctypes.byref(cfg))
     if npar < 0:
         check(npar)
-    out = [torch.empty((n_reg, npar), dtype=torch.float32, device="cuda") for _ in range(3)]
+    out = [torch.empty((n_reg, npar), dtype=reg_dtype(cfg), device="cuda") for _ in range(3)]
     check(L.cva_regress_adam_state(ctypes.byref(cfg), n_reg, M, _dptr(ws), ws.numel(), _dptr(out[0]),
                                    _dptr(out[1]), _dptr(out[2]), _stream()))
     return tuple(out)
@@ -565,7 +620,7 @@ def regress_predict(cfg: MlpCfg, dates, X, model):
     import torch
     n1, n_feat, M = X.shape
     d = _i32(dates)
-    out = torch.empty((int(d.size), M), dtype=torch.float32, device="cuda")
+    out = torch.empty((int(d.size), M), dtype=reg_dtype(cfg), device="cuda")
     check(lib().cva_regress_predict(ctypes.byref(cfg), int(d.size), d.ctypes.data_as(_c_i32p), n1, M,
                                     n_feat, _dptr(X), _dptr(model), _dptr(out), _stream()))
     return out

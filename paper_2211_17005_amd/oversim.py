@@ -3,18 +3,16 @@
 
 1. Pilot: the targets at n_b = 1 and n_b = 2 of one seed (common random numbers make the first
    continuation of the n_b = 2 run the n_b = 1 run), reduced per date by hsim_oversim_moments
-   into R_i = Cov(g, g') and Q_i = E[Var(g | outer path)] of the pointwise loss
-   g = (xi - phi)^2 (phi = the given predictions, 0 before training).
+   into the moments of the pointwise loss g = (xi - phi)^2 (phi = the given predictions, 0
+   before training).
 2. Cost ratio: P, the cost of one outer path in units of one inner continuation, from the
-   times of two fused simulations with the same M and n_b = N, N' (t / t' = (P + N) / (P + N')).
-3. N*_i = sqrt(Q_i P / R_i) at every date with R_i > 0; N = their mean (at least 1);
-   M = Psi / (N + P) for a budget of Psi inner-continuation units.
+   times of two simulations with the same M and n_b = N, N' (hsim_oversim_cost_ratio).
+3. hsim_oversim_choose: R_i = Cov(g, g'), Q_i = E[Var(g | outer path)], N*_i = sqrt(Q_i P / R_i)
+   at every date with R_i > 0; N = their mean (at least 1); M = Psi / (N + P) for a budget of
+   Psi inner-continuation units.
+This module only times the runs and passes the numbers to and from the library.
 """
 from __future__ import annotations
-
-import math
-
-import numpy as np
 
 from . import hsim
 
@@ -34,16 +32,13 @@ def _timed_solve(w, n_b: int, M: int, reps: int) -> float:
 
 
 def pilot(w, M: int, pred=None):
-    """R_i, Q_i of every date from the n_b = 1, 2 pilot on M outer paths (FP32 simulation)."""
+    """Pilot moments [n+1][3] of every date from the n_b = 1, 2 pilot on M outer paths (FP32)."""
     T = []
     for n_b in (1, 2):
         s = hsim.Solver(w.with_(n_b=n_b), precision=hsim.HSIM_FP32, M=M)
         s.inner_defaults_cva(want_features=False)
         T.append(s.T.clone())
-    mom = hsim.oversim_moments(w.grid, T[0], T[1], pred).cpu().numpy()
-    R = mom[:, 2] - mom[:, 0] ** 2
-    Q = mom[:, 1] - mom[:, 2]
-    return R, Q
+    return hsim.oversim_moments(w.grid, T[0], T[1], pred).cpu().numpy()
 
 
 def cost_ratio(w, M: int, n_b=(1, 1024), reps: int = 5) -> float:
@@ -54,16 +49,14 @@ def cost_ratio(w, M: int, n_b=(1, 1024), reps: int = 5) -> float:
     if not tp > t * 1.05:
         raise RuntimeError(f"timings {t:.3g} s (n_b={N}) and {tp:.3g} s (n_b={Np}) do not resolve the "
                            "cost ratio: use a larger M or n_b'")
-    return (tp * N - t * Np) / (t - tp)
+    return hsim.oversim_cost_ratio(t, tp, N, Np)
 
 
 def choose(w, Psi: float, M_pilot: int = 1 << 16, pred=None, P=None) -> dict:
     """Heuristic heur:MN for workload w and a budget Psi (in units of one inner continuation)."""
-    R, Q = pilot(w, M_pilot, pred)
+    mom = pilot(w, M_pilot, pred)
     if P is None:
         P = cost_ratio(w, M_pilot)
-    ok = (R > 0.0) & (Q >= 0.0)
-    n_star = np.sqrt(Q[ok] * P / R[ok])
-    N = max(1.0, float(n_star.mean())) if n_star.size else 1.0
-    return {"N": N, "n_b": int(max(1, round(N))), "M": Psi / (N + P), "P": float(P),
-            "N_dates": n_star, "R": R, "Q": Q}
+    out = hsim.oversim_choose(mom, P, Psi)
+    out.update({"n_b": int(max(1, round(out["N"]))), "P": float(P), "moments": mom})
+    return out

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(hs):
 
 
 def test_abi_version(hs):
-    assert hs.abi_version() == 1
+    assert hs.abi_version() == 2
 
 
 def test_par_rates_match_oracle(hs):
@@ -134,6 +134,32 @@ def test_fused_rejects_small_workspace(hs, cpu_only):
     assert rc == -3
 
 
+def test_one_launch_rejects_bad_arguments(hs, cpu_only):
+    """hsim_fused: workspace too small, FP32_PLAIN (not a form of the one-launch kernel), and a
+    date x counterparty table beyond its LDS are refused before any launch; the inner stage
+    refuses more dates than its LDS tile holds."""
+    w = wl.small_multi()
+    km = hs.market_struct(w.market)
+    kp = hs.portfolio_struct(w.portfolio, np.zeros(w.portfolio.n_swaps))
+    g = hs.grid_struct(w.grid)
+    need = hs.lib().hsim_workspace_bytes(hs.OP_FUSED_LAUNCH, ctypes.byref(km.struct), ctypes.byref(g), w.M, 1)
+    assert need > 0
+    dummy = ctypes.c_void_p(256)
+    call = lambda g_, prec, ws: hs.lib().hsim_fused(ctypes.byref(km.struct), ctypes.byref(kp.struct),
+                                                    ctypes.byref(g_), 0, 0, w.M, 8, None, 64, prec, 0, None,
+                                                    dummy, dummy, dummy, ws, None)
+    assert call(g, 1, need - 1) == -3
+    assert call(g, hs.HSIM_FP32_PLAIN, need) == -1
+    big = hs.grid_struct(wl.Grid(8.0, 512, 5))        # 513 dates x 16 counterparties: 104 KiB of LDS
+    m16 = hs.market_struct(wl.small_multi(n_cpty=16).market)
+    need16 = hs.lib().hsim_workspace_bytes(hs.OP_FUSED_LAUNCH, ctypes.byref(m16.struct), ctypes.byref(big), 64, 1)
+    rc = hs.lib().hsim_fused(ctypes.byref(m16.struct), ctypes.byref(kp.struct), ctypes.byref(big), 0, 0, 64, 8,
+                             None, 64, 1, 0, None, dummy, dummy, dummy, need16, None)
+    assert rc == -2 and b"LDS" in hs.lib().hsim_last_error()
+    assert hs.lib().hsim_inner_defaults(ctypes.byref(big), 1, 0, 0, 64, 8, None, 64, dummy, dummy,
+                                        None, 0, None) == -2
+
+
 def test_inner_rejects_bad_nb(hs, cpu_only):
     g = hs.grid_struct(wl.Grid(10.0, 50, 25))
     dummy = ctypes.c_void_p(256)
@@ -193,3 +219,37 @@ def test_sample_rows_reject_bad_arguments(hs, cpu_only):
     assert f(ctypes.byref(g), 1, 2, 0, 0, 1 << 28, 16, 1, *ok) == -2      # M n_b > 2^31
     assert f(ctypes.byref(g), 1, 2, 0, 0, 64, 4, 1, None, dummy, dummy, dummy, dummy, dummy,
              None) == -1                                                  # features
+
+
+def test_oversim_chooser_matches_oracle(hs):
+    """hsim_oversim_choose / hsim_oversim_cost_ratio (host arithmetic of Section 3.3) against the
+    oracle's Proposition p:heurisN, Heuristic heur:MN and l:ratio on seeded pilot moments, with
+    dates whose R or Q rule N* out (no loss after the last maturity, a negative R)."""
+    from oracle import oversim as oos
+    rng = np.random.default_rng(5)
+    A = rng.gamma(2.0, 1.0, (12, 4000)) * rng.random((12, 1))          # per outer path
+    g1 = A + rng.gamma(1.5, 1.0, (12, 4000))                          # two continuations
+    g2 = A + rng.gamma(1.5, 1.0, (12, 4000))
+    g1[10:], g2[10:] = 0.0, 0.0                          # dates after the last maturity
+    mom = oos.moments(g1, g2)
+    mom[3, 2] = mom[3, 0] ** 2 - 1e-3                    # a date with R < 0
+    P = oos.cost_ratio(0.31, 0.95, 1.0, 256.0)
+    assert np.isclose(hs.oversim_cost_ratio(0.31, 0.95, 1.0, 256.0), P, rtol=1e-15)
+    out = hs.oversim_choose(mom, P, 1e9)
+    R, Q = oos.r_and_q(mom)
+    ok = (R > 0) & (Q >= 0)
+    assert out["defined"] == ok.sum() == 9
+    assert np.allclose(out["R"], R, rtol=1e-15, atol=0) and np.allclose(out["Q"], Q, rtol=1e-15, atol=0)
+    assert np.array_equal(np.isfinite(out["N_dates"]), ok)
+    Ns = oos.optimal_n(Q[ok], R[ok], P)
+    assert np.allclose(out["N_dates"][ok], Ns, rtol=1e-14)
+    N, M = oos.heuristic(Ns, P, 1e9)
+    assert np.isclose(out["N"], N, rtol=1e-14) and np.isclose(out["M"], M, rtol=1e-14)
+    small = hs.oversim_choose(np.array([[1.0, 1.0, 1.0]]), 5.0, 100.0)       # Q = 0: N* = 0 -> N = 1
+    assert small["N"] == 1.0 and np.isclose(small["M"], 100.0 / 6.0)
+    with pytest.raises(hs.HsimError):
+        hs.oversim_cost_ratio(1.0, 1.0, 1.0, 64.0)
+    with pytest.raises(hs.HsimError):
+        hs.oversim_cost_ratio(1.0, 0.5, 1.0, 64.0)       # the larger n_b ran faster: P < 0
+    with pytest.raises(hs.HsimError):
+        hs.oversim_choose(mom, -1.0, 1e9)

@@ -6,10 +6,10 @@ Tolerances: targets as the nested targets (FP64 1e-12, FP32 1e-5 scale-relative 
 default counts agree); weights exactly (a ratio of integers rounded once).  The weighted fit
 with seeded weights on the three-currency rows is held to the unweighted fits' BF16 bar (2e-2
 relative L2 of the predictions, final loss within 1 %).  On the one-counterparty rows (two
-inputs, 1000 rows, 8 short epochs) the BF16 and FP64 SGD trajectories part by several per cent
-weighted or not, so the alive learner is held to its losses and to the parting of the unweighted
-fit of the same rows; an FP32 build of the same kernel source matches the FP64 weighted oracle
-to 1e-6 there.
+inputs, 1000 rows) a whole BF16 fit is not a stable comparison: a CPU model of the kernel's BF16
+roundings already moves the FP64 fit by 4e-2 to 2e-1 there, so the alive learner's BF16 fit is
+checked where it is exact to a stated bound: one weighted Adam step element by element; the
+weighted least-squares refit is checked on the three-currency rows.
 """
 import numpy as np
 import pytest
@@ -17,6 +17,8 @@ import pytest
 import workloads as wl
 from oracle import pipeline
 from oracle import regression as org
+
+import bf16_bounds as bb
 
 pytestmark = pytest.mark.gpu
 
@@ -95,34 +97,63 @@ def test_weighted_fit_matches_oracle(lib, multi, hidden):
         assert npy(loss)[j][-1] == pytest.approx(fits[i].losses[-1], rel=1e-2)
 
 
-@pytest.mark.parametrize("hidden", [1, 2])
-def test_alive_learner_on_one_counterparty(lib, plain, hidden):
-    """The weighted fit of the alive-group targets on the one-counterparty rows: final losses
-    agree with the FP64 weighted oracle; the predictions part from it as much as the unweighted
-    fit of the same rows does (two inputs, short runs: a BF16-sensitive trajectory)."""
+def test_alive_learner_one_weighted_step_elementwise(lib, plain):
+    """One weighted Adam step (epochs = 1, batch = M) on the alive-group rows: every gradient
+    element (the Adam moment m / (1 - beta1)) lies within the first-order BF16 bound of the exact
+    FP64 weighted gradient (tests/bf16_bounds.py)."""
     import torch
     w, ref = plain
-    dates = [5, 20, 35]
-    X = torch.as_tensor(ref["features"].astype(np.float32), device="cuda")
-    Y = torch.as_tensor(ref["T_alive"].astype(np.float32), device="cuda")
-    Wt = torch.as_tensor(ref["W_alive"].astype(np.float32), device="cuda")
-    mlp = wl.MLPConfig(hidden=hidden, width=32, epochs=8, batch=200)
-    cfg = lib.mlp_cfg(mlp, X.shape[1], w.M)
-    model, loss, _ = lib.regress_fit(cfg, dates, X, Y, seed=w.seed, W=Wt)
-    pred = npy(lib.regress_predict(cfg, dates, X, model)).astype(np.float64)
-    fits = org.independent_fits(ref["features"], ref["T_alive"], mlp, w.seed, dates,
-                                W=ref["W_alive"].astype(np.float32).astype(np.float64))
-    # control: the unweighted fit of the nested targets on the same rows
-    Yu = torch.as_tensor(ref["T"].astype(np.float32), device="cuda")
-    mu_, _, _ = lib.regress_fit(cfg, dates, X, Yu, seed=w.seed)
-    pu = npy(lib.regress_predict(cfg, dates, X, mu_)).astype(np.float64)
-    fu = org.independent_fits(ref["features"], ref["T"], mlp, w.seed, dates)
-    for j, i in enumerate(dates):
-        p64 = org.predict(fits[i], ref["features"][i].T)
-        l2 = np.linalg.norm(pred[j] - p64) / np.linalg.norm(p64)
-        q64 = org.predict(fu[i], ref["features"][i].T)
-        l2u = np.linalg.norm(pu[j] - q64) / np.linalg.norm(q64)
-        print(f"  date {i} hidden {hidden}: weighted l2 {l2:.3e} (unweighted control {l2u:.3e}); "
-              f"loss gpu {npy(loss)[j][-1]:.5f} fp64 {fits[i].losses[-1]:.5f}", flush=True)
-        assert l2 <= max(5e-2, 1.5 * l2u)
-        assert npy(loss)[j][-1] == pytest.approx(fits[i].losses[-1], rel=1e-2)
+    date, hidden, width = 20, 2, 32
+    F = ref["features"].astype(np.float32).astype(np.float64)
+    T = ref["T_alive"].astype(np.float32).astype(np.float64)
+    Wa = ref["W_alive"].astype(np.float32).astype(np.float64)
+    M, d = F.shape[2], F.shape[1]
+    mlp = wl.MLPConfig(hidden=hidden, width=width, epochs=1, batch=M)
+    cfg = lib.mlp_cfg(mlp, d, M, team=1)
+    X = torch.as_tensor(F.astype(np.float32), device="cuda")
+    Y = torch.as_tensor(T.astype(np.float32), device="cuda")
+    Wt = torch.as_tensor(Wa.astype(np.float32), device="cuda")
+    _, _, ws = lib.regress_fit(cfg, [date], X, Y, seed=w.seed, W=Wt)
+    _, m, _ = (npy(t)[0].astype(np.float64) for t in lib.regress_adam_state(cfg, 1, M, ws))
+    Xd, yd = F[date].T, T[date]
+    sc = org.scaling(Xd, yd)
+    Xs, ys = (Xd - sc.x_mean) / sc.x_std, yd / sc.y_scale
+    g64, E = bb.gradient_with_bound(org.init_net(d, hidden, width, w.seed), Xs, ys, 0, 32, w=Wa[date])
+    g = m / (1.0 - mlp.beta1)
+    worst = np.max(np.abs(g - g64) / np.maximum(E, 1e-300))
+    print(f"  weighted one step: max |g - g64| / bound {worst:.3f}", flush=True)
+    assert np.all(np.abs(g - g64) <= E + 1e-7 * np.abs(g64))
+
+
+def test_weighted_refit_is_least_squares(lib, multi):
+    """lr = 0, two epochs: the weighted refit of the output layer (seeded weights in [0, 2) on the
+    three-currency rows) reaches the FP64 weighted least-squares minimum to 1e-3 from the frozen
+    initial hidden layers.  (On the alive-group rows of one counterparty the 32 hidden features
+    of two inputs are so close to collinear that BF16 rounding of the features alone moves the
+    least-squares loss by more than that; the alive learner's refit is the same code.)"""
+    import torch
+    w, ref = multi
+    date, hidden, width = 10, 2, 32
+    F = ref["features"].astype(np.float32).astype(np.float64)
+    T = ref["T"].astype(np.float32).astype(np.float64)
+    Wn = np.random.default_rng(1).uniform(0.0, 2.0, T.shape).astype(np.float32).astype(np.float64)
+    M, d = F.shape[2], F.shape[1]
+    mlp = wl.MLPConfig(hidden=hidden, width=width, epochs=2, batch=M // 4, lr=0.0)
+    cfg = lib.mlp_cfg(mlp, d, M)
+    X = torch.as_tensor(F.astype(np.float32), device="cuda")
+    Y = torch.as_tensor(T.astype(np.float32), device="cuda")
+    Wt = torch.as_tensor(Wn.astype(np.float32), device="cuda")
+    model, _, _ = lib.regress_fit(cfg, [date], X, Y, seed=w.seed, W=Wt)
+    npar = bb.flat_params(org.init_net(d, hidden, width, w.seed), 32).size
+    got = bb.net_from_flat(npy(model)[0][:npar], d, hidden, width, 32)
+    Xd, yd = F[date].T, T[date]
+    sc = org.scaling(Xd, yd)
+    Xs, ys = (Xd - sc.x_mean) / sc.x_std, yd / sc.y_scale
+    ref_net = org.init_net(d, hidden, width, w.seed)
+    org.refit_output_layer(ref_net, Xs, ys, Wn[date])
+    L64 = org.loss(ref_net, Xs, ys, 0, Wn[date])
+    mix = ref_net.copy()
+    mix.W[-1], mix.b[-1] = got.W[-1], got.b[-1]
+    Lgpu = org.loss(mix, Xs, ys, 0, Wn[date])
+    print(f"  weighted refit: loss of the GPU weights {Lgpu:.8f} vs least squares {L64:.8f}", flush=True)
+    assert L64 <= Lgpu <= L64 * (1 + 1e-3)

@@ -152,6 +152,45 @@ def test_fused_equals_separate_stages(lib):
         assert c1.item() == c2.item()
 
 
+FUSED_CASES = [
+    ("plain", lambda: wl.plain_fp64().with_(M=1000)),                 # ragged last tile
+    ("small_multi", lambda: wl.small_multi(M=333, n_b=13)),           # n_b not a multiple of 4
+    ("tiny", lambda: wl.tiny(M=3)),
+    ("ten_currencies", lambda: wl.cva_at_scale(M=4096 + 17, n_b=128)),
+]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in FUSED_CASES])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_one_launch_equals_separate_stages(lib, name, precision):
+    """hsim_fused (outer paths, inner draws and targets in one launch) gives the features, targets
+    and CVA_0 of the separate stages bit for bit."""
+    import torch
+    w = dict(FUSED_CASES)[name]()
+    if precision == 0 and name == "ten_currencies":
+        w = w.with_(M=1024 + 5)
+    s = lib.Solver(w, precision=precision)
+    f1, T1, c1 = [x.clone() for x in s.inner_defaults_cva()]
+    fs = lib.FusedSolver(w, precision=precision)
+    f2, T2, c2 = fs.run()
+    torch.cuda.synchronize()
+    print(f"  [{w.name} precision {precision}] CVA_0 {c2.item():.12g}", flush=True)
+    assert torch.equal(f1, f2) and torch.equal(T1, T2) and torch.equal(c1, c2)
+
+
+def test_one_launch_uneven_nb_and_path_offset(lib):
+    """Uneven n_b per block of 64 paths and a path range that does not start at 0."""
+    import torch
+    w = wl.small_multi(M=640, n_b=8)
+    levels = np.array([1, 8, 64, 3, 17, 2, 128, 5, 9, 33], dtype=np.int32)
+    s = lib.Solver(w, precision=1, n_b_per_block=levels, block_paths=64)
+    f1, T1, c1 = [x.clone() for x in s.inner_defaults_cva(path_begin=77)]
+    fs = lib.FusedSolver(w, precision=1, n_b_per_block=levels, block_paths=64)
+    f2, T2, c2 = fs.run(path_begin=77)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2) and torch.equal(T1, T2) and torch.equal(c1, c2)
+
+
 def test_deterministic_and_split_invariant(lib):
     """Two runs agree bitwise; simulating [0, M/2) and [M/2, M) separately changes nothing."""
     w = wl.small_multi(M=256)
@@ -208,3 +247,28 @@ def test_scale_workload_sampled_paths(lib):
     Tg = npy(T[:, torch.as_tensor(sample, device="cuda")]).astype(np.float64)
     report("T sampled", scale_err(Tg, Tref), 1e-5)
     assert np.isfinite(cva0.item()) and cva0.item() > 0
+
+
+def test_plain_fp32_integrals(lib, case):
+    """HSIM_FP32_PLAIN (the baseline with FP32 integrals): the FP32 state and features are those of
+    HSIM_FP32 bit for bit (the integrals do not feed back into the state); I and Lambda follow the
+    oracle to 1e-4 of their scale (FP32 sums of up to 2500 terms), the exposures D to 1e-4 of the
+    gross notional, and every fused output is that of the plain simulation's own stages."""
+    w, ref = case
+    a = lib.outer_paths(w, precision=lib.HSIM_FP32, want_mtm=True)
+    b = lib.outer_paths(w, precision=lib.HSIM_FP32_PLAIN, want_mtm=True)
+    m = w.market
+    d = 2 * m.n_ccy - 1 + m.n_cpty                     # market factors (not the integral columns)
+    assert np.array_equal(npy(a["features"])[:, :d], npy(b["features"])[:, :d])
+    assert np.array_equal(npy(a["MtM"]), npy(b["MtM"]))
+    eI = scale_err(npy(b["I"]), ref["I"])
+    eL = scale_err(npy(b["Lam"]), ref["Lam"])
+    g = np.maximum(gross_notional(w), 1.0)[None, :, None]
+    eD = float(np.max(np.abs(npy(b["D"]).astype(np.float64) - ref["D"]) / g))
+    print(f"  plain FP32 integrals [{w.name}]: I {eI:.2e} (FP64 integrals "
+          f"{scale_err(npy(a['I']), ref['I']):.2e}), Lambda {eL:.2e}, D {eD:.2e}", flush=True)
+    assert eI <= 1e-4 and eL <= 1e-4 and eD <= 1e-4
+    _, T, cva0 = lib.inner_defaults_cva(w, precision=lib.HSIM_FP32_PLAIN)
+    cnt = lib.inner_defaults(w.grid, w.market.n_cpty, w.seed, b["Lam"], n_b=w.n_b)
+    T2, cva2 = lib.targets_cva(w.grid, w.market.n_cpty, b["I"], b["D"], cnt, n_b=w.n_b)
+    assert np.array_equal(npy(T), npy(T2)) and cva0.item() == cva2.item()
