@@ -362,7 +362,9 @@ size_t hsim_workspace_bytes(int op, const hsim_market* market, const hsim_grid* 
 typedef struct {
   int32_t hidden;     /* hidden layers; built shapes (width, hidden): (32,1) (32,2) (64,2) (128,2) (128,3) */
   int32_t width;      /* units per hidden layer */
-  int32_t d_in;       /* inputs per row, 1..32 (the first d_in features of X) */
+  int32_t d_in;       /* inputs per row (the first d_in features of X): 1..32; up to 64 with
+                         HSIM_REG_FP32 / HSIM_REG_FP64 (the model record then pads W_1 and the
+                         scaling to 64 columns instead of 32) */
   int32_t epochs;     /* E >= 1 */
   int32_t batch;      /* rows per SGD batch; the last batch of an epoch may be shorter */
   double lr, beta1, beta2, eps; /* Adam (lr >= 0; lr = 0 leaves the network as initialised); the
@@ -390,9 +392,9 @@ enum { HSIM_REG_BF16 = 0, HSIM_REG_FP32 = 1, HSIM_REG_FP64 = 2 };
 int cva_regress_record_floats(const cva_mlp_cfg* cfg);
 
 /* Elements of the parameters at the head of a model record, in the order
- * W_1 [width][32] (columns >= d_in zero), b_1, W_2 [width][width], b_2, ..., W_hidden, b_hidden,
- * w_out [width], b_out, mu; the record continues with the input means [32], the inverse standard
- * deviations [32], the target scale and a trained flag. */
+ * W_1 [width][D] (columns >= d_in zero), b_1, W_2 [width][width], b_2, ..., W_hidden, b_hidden,
+ * w_out [width], b_out, mu; the record continues with the input means [D], the inverse standard
+ * deviations [D], the target scale and a trained flag.  D = 32 for d_in <= 32, else 64. */
 int cva_regress_param_floats(const cva_mlp_cfg* cfg);
 
 /* Device workspace for cva_regress_fit. */

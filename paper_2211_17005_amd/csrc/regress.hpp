@@ -14,23 +14,27 @@ constexpr int kMaxRegDates = 512;
 constexpr int kTeamSpinLimit = 1 << 22;  // default polls before a bounded wait gives up (several seconds)
 constexpr double kRefitGuard = 1e-12; // refit: a Cholesky pivot at or below this times its diagonal drops the column
 
-// Layout of one date's model record (floats):
-//   [ W_1 (U x 32) | b_1 (U) | W_2 (U x U) | b_2 | ... | W_H | b_H | w_out (U) | b_out | mu |
-//     x_mean (32) | x_inv_std (32) | y_scale | trained ]
+// Layout of one date's model record (floats; doubles on the FP64 path), D = the padded input
+// width (32, or 64 on the FP32 / FP64 path for 33..64 inputs):
+//   [ W_1 (U x D) | b_1 (U) | W_2 (U x U) | b_2 | ... | W_H | b_H | w_out (U) | b_out | mu |
+//     x_mean (D) | x_inv_std (D) | y_scale | trained ]
 // W_1 columns >= d_in stay zero.  Prediction: ((f)^+ + mu) * y_scale, 0 when untrained.
+constexpr int kMlpDinWide = 64;
+__host__ __device__ inline int din_pad(int d_in) { return d_in <= kMlpDin ? kMlpDin : kMlpDinWide; }
+
 struct MlpLayout {
-  int U, H;
+  int U, H, D = kMlpDin;
   __host__ __device__ int w_off(int l) const {   // l = 1..H
-    return l == 1 ? 0 : U * kMlpDin + U + (l - 2) * (U * U + U);
+    return l == 1 ? 0 : U * D + U + (l - 2) * (U * U + U);
   }
-  __host__ __device__ int b_off(int l) const { return w_off(l) + U * (l == 1 ? kMlpDin : U); }
+  __host__ __device__ int b_off(int l) const { return w_off(l) + U * (l == 1 ? D : U); }
   __host__ __device__ int wout_off() const { return b_off(H) + U; }
   __host__ __device__ int bout_off() const { return wout_off() + U; }
   __host__ __device__ int mu_off() const { return bout_off() + 1; }
   __host__ __device__ int n_params() const { return mu_off() + 1; }
   __host__ __device__ int xmean_off() const { return n_params(); }
-  __host__ __device__ int xinv_off() const { return xmean_off() + kMlpDin; }
-  __host__ __device__ int yscale_off() const { return xinv_off() + kMlpDin; }
+  __host__ __device__ int xinv_off() const { return xmean_off() + D; }
+  __host__ __device__ int yscale_off() const { return xinv_off() + D; }
   __host__ __device__ int trained_off() const { return yscale_off() + 1; }
   __host__ __device__ int record() const { return trained_off() + 1; }
 };

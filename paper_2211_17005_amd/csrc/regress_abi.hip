@@ -25,7 +25,8 @@ int check_cfg(const cva_mlp_cfg* c) {
   } else if (!mlp_supported(c->width, c->hidden)) {
     return fail(HSIM_EUNSUPPORTED, "no kernel built for width=%d hidden=%d", c->width, c->hidden);
   }
-  if (c->d_in < 1 || c->d_in > kMlpDin) return fail(HSIM_ERANGE, "d_in=%d out of [1,%d]", c->d_in, kMlpDin);
+  const int dmax = plain(c) ? kMlpDinWide : kMlpDin;
+  if (c->d_in < 1 || c->d_in > dmax) return fail(HSIM_ERANGE, "d_in=%d out of [1,%d]", c->d_in, dmax);
   if (c->epochs < 1 || c->batch < 1) return fail(HSIM_EINVAL, "epochs and batch must be >= 1");
   if (c->team < 0 || c->team > 32) return fail(HSIM_ERANGE, "team=%d out of [0,32]", c->team);
   if (!(c->lr >= 0.0) || !(c->beta1 >= 0.0 && c->beta1 < 1.0) || !(c->beta2 >= 0.0 && c->beta2 < 1.0) ||
@@ -155,7 +156,7 @@ int cva_regress_adam_state(const cva_mlp_cfg* c, int32_t n_reg, int64_t M, const
   if (!workspace_dev || ws_bytes < cva_regress_workspace_bytes(c, n_reg, M))
     return fail(HSIM_ENOWS, "workspace smaller than the fit's");
   // both paths keep the parameters, then m, then v of every date at the head of the workspace
-  const size_t bytes = (size_t)MlpLayout{c->width, c->hidden}.n_params() * n_reg * elem_bytes(c);
+  const size_t bytes = (size_t)MlpLayout{c->width, c->hidden, din_pad(c->d_in)}.n_params() * n_reg * elem_bytes(c);
   const char* src = (const char*)workspace_dev;
   void* dst[3] = {params_dev, m_dev, v_dev};
   for (int k = 0; k < 3; ++k) {
@@ -170,13 +171,13 @@ int cva_regress_adam_state(const cva_mlp_cfg* c, int32_t n_reg, int64_t M, const
 int cva_regress_param_floats(const cva_mlp_cfg* c) {
   int rc = check_cfg(c);
   if (rc) return rc;
-  return MlpLayout{c->width, c->hidden}.n_params();
+  return MlpLayout{c->width, c->hidden, din_pad(c->d_in)}.n_params();
 }
 
 int cva_regress_record_floats(const cva_mlp_cfg* c) {
   int rc = check_cfg(c);
   if (rc) return rc;
-  return MlpLayout{c->width, c->hidden}.record();
+  return MlpLayout{c->width, c->hidden, din_pad(c->d_in)}.record();
 }
 
 size_t cva_regress_workspace_bytes(const cva_mlp_cfg* c, int32_t n_reg, int64_t M) {

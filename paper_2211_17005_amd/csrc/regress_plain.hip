@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kPB) void plain_stats(const T* X, const T* Y, int64
     const double ys = sqrt(x2 * inv_m);
     rec[L.yscale_off()] = (T)ys;
     rec[L.trained_off()] = ys > 0.0 ? (T)1 : (T)0;
-    for (int p = d_in; p < kMlpDin; ++p) {
+    for (int p = d_in; p < L.D; ++p) {
       rec[L.xmean_off() + p] = (T)0;
       rec[L.xinv_off() + p] = (T)1;
     }
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kPB) void plain_init(T* P, T* Mm, T* Vv, const T* p
     if (e < L.wout_off()) {
       for (l = L.H; l >= 1 && e < L.w_off(l); --l) {
       }
-      const int stride = l == 1 ? kMlpDin : L.U;
+      const int stride = l == 1 ? L.D : L.U;
       if (e < L.b_off(l)) {
         o = (e - L.w_off(l)) / stride;
         i = (e - L.w_off(l)) % stride;
@@ -376,17 +376,18 @@ struct PlainBufs {
 
 template <typename T>
 PlainBufs plain_layout(const cva_mlp_cfg* c, int n_reg, int64_t M) {
-  const MlpLayout L{c->width, c->hidden};
+  const MlpLayout L{c->width, c->hidden, din_pad(c->d_in)};
   const int64_t batch = std::min<int64_t>(c->batch, M);
   PlainBufs b;
   b.C = std::max<int64_t>(batch, std::min<int64_t>(M, kPlainChunk));
   const size_t np = (size_t)L.n_params(), C = (size_t)b.C, U = (size_t)c->width, N = U + 1;
-  const size_t dmax = std::max<size_t>(U, kMlpDin);
+  const size_t D = (size_t)din_pad(c->d_in);
+  const size_t dmax = std::max<size_t>(U, D);
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t r = o; o += align256(bytes); return r; };
   b.o_state = take(3 * np * n_reg * sizeof(T));            // parameters, m, v of every date
   b.o_grad = take(np * sizeof(T));
-  b.o_act = take((kMlpDin + c->hidden * U) * C * sizeof(T));  // A_0, A_1 .. A_H
+  b.o_act = take((D + c->hidden * U) * C * sizeof(T));  // A_0, A_1 .. A_H
   b.o_d0 = take(dmax * C * sizeof(T));
   b.o_d1 = take(dmax * C * sizeof(T));
   b.o_vec = take(4 * C * sizeof(T));                       // f, df, y, w
@@ -426,7 +427,7 @@ struct PlainRun {
 
   void bind() {
     A0 = (T*)(ws + b.o_act);
-    for (int l = 0; l < 3; ++l) Al[l] = A0 + (size_t)kMlpDin * b.C + (size_t)l * L.U * b.C;
+    for (int l = 0; l < 3; ++l) Al[l] = A0 + (size_t)L.D * b.C + (size_t)l * L.U * b.C;
     d0 = (T*)(ws + b.o_d0);
     d1 = (T*)(ws + b.o_d1);
     f = (T*)(ws + b.o_vec);
@@ -448,7 +449,7 @@ struct PlainRun {
                        n_feat, d_in, date, r0, n, rec, L, A0, with_targets ? y : (T*)nullptr, w);
     launched("input staging");
     const T* in = A0;
-    int K = d_in, ldw = kMlpDin;
+    int K = d_in, ldw = L.D;
     for (int l = 1; l <= L.H; ++l) {
       blas(Blas<T>::gemm(h, rocblas_operation_transpose, rocblas_operation_none, L.U, n, K, P + L.w_off(l), ldw, in,
                          K, (T)0, Al[l - 1], L.U),
@@ -480,7 +481,7 @@ struct PlainRun {
     T* da = d1;
     for (int l = L.H; l >= 1; --l) {
       const T* in = l == 1 ? A0 : Al[l - 2];
-      const int K = l == 1 ? d_in : L.U, ldw = l == 1 ? kMlpDin : L.U;
+      const int K = l == 1 ? d_in : L.U, ldw = l == 1 ? L.D : L.U;
       blas(Blas<T>::gemm(h, rocblas_operation_none, rocblas_operation_transpose, K, L.U, n, in, K, dz, L.U, (T)0,
                          G + L.w_off(l), ldw),
            "weight-gradient GEMM");
@@ -542,7 +543,7 @@ int plain_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int64_t
               hipStream_t s) {
   PlainRun<T> R;
   R.c = c;
-  R.L = MlpLayout{c->width, c->hidden};
+  R.L = MlpLayout{c->width, c->hidden, din_pad(c->d_in)};
   R.s = s;
   R.M = M;
   R.n_feat = n_feat;
@@ -621,7 +622,7 @@ int plain_predict(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int
   // predictions need only the input buffers: a one-date layout without training state
   PlainRun<T> R;
   R.c = c;
-  R.L = MlpLayout{c->width, c->hidden};
+  R.L = MlpLayout{c->width, c->hidden, din_pad(c->d_in)};
   R.s = s;
   R.M = M;
   R.n_feat = n_feat;

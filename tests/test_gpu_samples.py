@@ -109,3 +109,37 @@ def test_literal_regression_on_the_rows_matches_oracle(lib):
               flush=True)
         assert l2 <= 2e-2
         assert npy(loss)[j][-1] == pytest.approx(fits[i].losses[-1], rel=1e-2)
+
+
+@pytest.mark.timeout(900)
+def test_paper_sized_rows_35_inputs(lib):
+    """The paper's per-inner-sample regression at its own input size: the ten-currency market
+    (27 factors) and 8 counterparties (8 default indicators) give 35 inputs.  The rows of the
+    first 256 paths x 4 draws equal the oracle's (indicators exactly, labels to float rounding),
+    and the FP64 regression path fits them as the oracle's FP64 BaseAlg does (1e-6)."""
+    import torch
+    w = wl.cva_at_scale(M=256, n_b=4).with_(features="factors")
+    Xr, Yr, _ = oracle_rows(w)
+    out = lib.outer_paths(w, precision=0)
+    X, Y = lib.sample_rows(w, out, precision=0)
+    d = out["features"].shape[1]
+    assert X.shape[1] == 35 and d == 27
+    Xn, Yn = npy(X).astype(np.float64), npy(Y).astype(np.float64)
+    assert np.array_equal(Xn[:, d:], Xr[:, d:])
+    assert np.max(np.abs(Yn - Yr)) <= 1e-6 * np.max(np.abs(Yr))
+    Xr32 = Xr.astype(np.float32).astype(np.float64)
+    Yr32 = Yr.astype(np.float32).astype(np.float64)
+    dates = [20, 60]
+    mlp = wl.MLPConfig(hidden=2, width=32, epochs=4, batch=256)
+    cfg = lib.mlp_cfg(mlp, 35, X.shape[2], dtype=lib.REG_FP64)
+    Xd = torch.as_tensor(Xr32, device="cuda")
+    Yd = torch.as_tensor(Yr32, device="cuda")
+    model_, loss, _ = lib.regress_fit(cfg, dates, Xd, Yd, seed=w.seed)
+    pred = npy(lib.regress_predict(cfg, dates, Xd, model_))
+    fits = org.independent_fits(Xr32, Yr32, mlp, w.seed, dates)
+    for j, i in enumerate(dates):
+        p64 = org.predict(fits[i], Xr32[i].T)
+        l2 = np.linalg.norm(pred[j] - p64) / np.linalg.norm(p64)
+        mx = np.max(np.abs(pred[j] - p64)) / np.max(np.abs(p64))
+        print(f"  35 inputs, date {i}: l2 {l2:.3e} max {mx:.3e}", flush=True)
+        assert l2 <= 1e-6 and mx <= 1e-6
