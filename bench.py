@@ -197,8 +197,8 @@ def cpu_baseline(w, name, kw, workers: int, n_sim: int, n_rows: int, n_sens: int
 # ------------------------------------------------------------------------------- plain FP32
 def plain_fp32_solve(hsim, torch, w, wr, wa, fixed, fast):
     """The plain FP32 form of the same solve, all in the library, timed stage by stage:
-    simulation with FP32 integrals (HSIM_FP32_PLAIN, separate stages), Backward learning
-    (Algorithm 2) over every trained date with the FP32 GEMM regression (REG_FP32), and CVA_0
+    simulation with FP32 integrals (HSIM_FP32_PLAIN, separate stages), BaseAlg at every trained
+    date, one date after another, with the FP32 GEMM regression (REG_FP32), and CVA_0
     sensitivities by central differences with common random numbers (relative bump 1e-4) of the
     smoothed estimator on the plain simulation of the sensitivity paths.  Then the accuracy of the
     two forms side by side: CVA_0 against one Monte Carlo standard error, the held-out mean
@@ -218,7 +218,9 @@ def plain_fp32_solve(hsim, torch, w, wr, wa, fixed, fast):
     sol = hsim.Solver(w, precision=hsim.HSIM_FP32_PLAIN, fixed=fixed)
     sol.inner_defaults_cva()                                   # untimed first call
     (feats, T, cva0), sim_s = timed(sol.inner_defaults_cva)
-    cfg = hsim.mlp_cfg(wr.mlp, d, M, warm_start=True, dtype=hsim.REG_FP32)
+    # the same algorithm as the fast form (BaseAlg from the common initial draw at every date), in
+    # FP32 and date after date, so that the accuracy comparison isolates the precision and the form
+    cfg = hsim.mlp_cfg(wr.mlp, d, M, warm_start=False, dtype=hsim.REG_FP32)
     (model, _, _), reg_s = timed(lambda: hsim.regress_fit(cfg, dates, feats, T, seed=w.seed, want_loss=False))
 
     base = hsim.pack_params(wa.market)
@@ -261,7 +263,7 @@ def plain_fp32_solve(hsim, torch, w, wr, wa, fixed, fast):
     return {"solve_s": plain_s, "simulation_s": sim_s, "regression_s": reg_s, "sensitivities_s": fd_s,
             "speedup_of_fast_form": plain_s / fast["solve_s"],
             "forms": {"simulation": "f32 with f32 integrals, separate stages",
-                      "regression": f"REG_FP32 rocBLAS path, Algorithm 2 over {len(dates)} dates",
+                      "regression": f"REG_FP32 rocBLAS path, BaseAlg date after date over {len(dates)} dates",
                       "sensitivities": f"central differences, 2 x {base.size} simulations of {wa.M} paths, "
                                        f"h = {h:g} relative, common random numbers"},
             "accuracy": {"cva0_fast": fast["cva0"], "cva0_plain": cva0.item(), "cva0_se": se,
@@ -375,6 +377,7 @@ def main():
     ap.add_argument("--sweep-M", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (scale of the FETCH/WRITE counters)")
+    ap.add_argument("--no-fused", action="store_true", help="skip the one-launch simulation line")
     ap.add_argument("--no-validation", action="store_true",
                     help="skip the twin / nested Monte Carlo check of the fitted network")
     args = ap.parse_args()
@@ -525,6 +528,26 @@ def main():
         plain = plain_fp32_solve(hsim, torch, w, wr, wa, fixed, fast)
         print(f"# plain FP32 form: {plain['solve_s']:.2f} s per solve", file=sys.stderr, flush=True)
 
+    fused = None
+    if not args.no_fused:
+        # the one-launch simulation (hsim_fused) on the same workload, outside the timed step:
+        # same features, targets and CVA_0 as the three stages above
+        fs = hsim.FusedSolver(w, precision=prec, fixed=fixed)
+        fs.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            fs.run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        split = stage_ms["outer"] + stage_ms["inner"] + stage_ms["targets"]
+        fused = {"ms": e0.elapsed_time(e1) / 3, "separate_stages_ms": split,
+                 "same_cva0": bool(fs.cva0.item() == cva0.item()),
+                 "same_targets": bool(torch.equal(fs.T, T)),
+                 "path_steps_per_s": path_steps / (e0.elapsed_time(e1) / 3 / 1e3)}
+        del fs
+
     sweep = None
     if not args.sim_only and not args.no_sweep:
         sweep = oversim_sweep(hsim, torch, args.sweep_M)
@@ -561,6 +584,7 @@ def main():
         "roofline_regression": mlp_roof,
         "cva0": cva0.item(),
         "plain_fp32": plain,
+        "fused_simulation": fused,
         "oversim_sweep": sweep,
         "validation": valid,
         "cpu_baseline": cpu,

@@ -3,7 +3,8 @@ indicator as X): the alive-group targets and weights of hsim_targets_alive, and 
 fit of cva_regress_fit, against the FP64 oracle.
 
 Tolerances: targets as the nested targets (FP64 1e-12, FP32 1e-5 scale-relative on paths whose
-default counts agree); weights exactly (a ratio of integers rounded once).  The weighted fit
+default counts agree with the oracle's, and on every path against the oracle's groups formed with
+the GPU's default dates); weights exactly (a ratio of integers rounded once).  The weighted fit
 with seeded weights on the three-currency rows is held to the unweighted fits' BF16 bar (2e-2
 relative L2 of the predictions, final loss within 1 %).  On the one-counterparty rows (two
 inputs, 1000 rows) a whole BF16 fit is not a stable comparison: a CPU model of the kernel's BF16
@@ -15,6 +16,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
+from oracle import inner as oinner
 from oracle import pipeline
 from oracle import regression as org
 
@@ -51,6 +53,16 @@ def test_alive_targets_match_oracle(lib, plain, precision, tol):
     print(f"  precision {precision}: T_alive err {err:.3e}, weights exact on {ok.sum()} paths")
     assert err <= tol
     assert np.array_equal(Wt[:, ok], ref["W_alive"][:, ok].astype(np.float32).astype(np.float64))
+    if precision == 1 and not ok.all():
+        # every path: the oracle's groups on its own I and MtM with the GPU's default dates
+        u = oinner.inner_draws(w, np.arange(w.M))
+        js = oinner.default_dates(np.transpose(npy(out["Lam"]), (0, 2, 1)), u)
+        xi = oinner.pathwise_loss(ref["I"], np.transpose(ref["MtM"], (0, 2, 1)), w.market.lgd, js)
+        ta, wa = oinner.alive_targets(xi, js)
+        err = scale_err(T, ta)
+        print(f"  precision 1, all {w.M} paths on the GPU's default dates: T_alive err {err:.3e}")
+        assert err <= tol
+        assert np.array_equal(Wt, wa.astype(np.float32).astype(np.float64))
     _, Tn, cva_n = lib.inner_defaults_cva(w, precision=precision)
     assert cva0.item() == cva_n.item()                  # everyone is alive at t_0
     assert np.array_equal(T[0], npy(Tn)[0].astype(np.float64))
