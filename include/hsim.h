@@ -408,7 +408,7 @@ size_t cva_regress_workspace_bytes(const cva_mlp_cfg* cfg, int32_t n_reg, int64_
  *   with the weights of hsim_targets_alive this is the grouped form of the paper's
  *   per-inner-sample regression, Section 3.2),
  * date index dates[j] (host array).  model_dev [n_reg][cva_regress_record_floats] receives
- * the best parameters and the input scaling; loss_hist_dev [n_reg][epochs] (may be NULL) the
+ * the best parameters and the input scaling (BF16 form: 8-byte aligned, else HSIM_EINVAL); loss_hist_dev [n_reg][epochs] (may be NULL) the
  * full-sample loss after every epoch (in units of the scaled targets).  n_reg <= 512.
  * The team barriers and the loss helpers' waits are bounded: should one give up (it cannot while
  * every workgroup of the cooperative launch is resident), the fit stops early and the call
@@ -432,7 +432,7 @@ int cva_regress_adam_state(const cva_mlp_cfg* cfg, int32_t n_reg, int64_t M, con
 int hsim_set_wait_limit(int32_t polls);
 
 /* Predictions out_dev [n_reg][M] = ((f)^+ + mu) * y_scale of the fitted networks on X_dev (float,
- * or double for HSIM_REG_FP64, as the fit's). */
+ * or double for HSIM_REG_FP64, as the fit's); model_dev as the fit's (BF16 form: 8-byte aligned). */
 int cva_regress_predict(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* dates, int32_t n_dates_total,
                         int64_t M, int32_t n_feat, const void* X_dev, const void* model_dev,
                         void* out_dev, void* stream);

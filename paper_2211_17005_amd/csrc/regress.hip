@@ -251,22 +251,29 @@ struct DwMap {
   static_assert(BO * BI == TW && NIB * NOB * TW == NT * KT && NIB * NOB <= kMlpWaves, "tiling");
 };
 
-// Weights of layer l from FP32 global memory into the BF16 LDS copy: each thread issues the
-// loads of kLoadBatch elements before it stores any of them (the copy is latency-bound otherwise).
+// Weights of layer l from FP32 global memory into the BF16 LDS copy, two consecutive inputs of
+// one output per thread and vector: an 8-byte global load (a network's parameters start 8-byte
+// aligned: their count is even) and one 4-byte LDS store; each thread issues the loads of a batch
+// of pairs before it stores any of them (the copy is latency-bound otherwise).
 template <int U, int H, int l>
 __device__ __forceinline__ void load_layer_weights(const Smem<U, H>& S, const float* __restrict__ src, int t) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
   constexpr int K = Smem<U, H>::ldk(l), SWl = Smem<U, H>::lds(l);
-  constexpr int PER = U * K / kMlpThreads, kLoadBatch = PER < 8 ? PER : 8;
-  static_assert(PER * kMlpThreads == U * K && PER % kLoadBatch == 0, "whole batches per thread");
+  constexpr int PER = U * K / (2 * kMlpThreads), kBatch = PER < 8 ? PER : 8;   // pairs per thread
+  static_assert(PER * 2 * kMlpThreads == U * K && PER % kBatch == 0, "whole batches of pairs per thread");
   __bf16* W = S.W(l);
-  for (int i0 = 0; i0 < PER; i0 += kLoadBatch) {
-    float v[kLoadBatch];
+  for (int i0 = 0; i0 < PER; i0 += kBatch) {
+    f32x2 v[kBatch];
 #pragma unroll
-    for (int i = 0; i < kLoadBatch; ++i) v[i] = src[t + (i0 + i) * kMlpThreads];
+    for (int i = 0; i < kBatch; ++i) v[i] = *(const f32x2*)&src[2 * (t + (i0 + i) * kMlpThreads)];
 #pragma unroll
-    for (int i = 0; i < kLoadBatch; ++i) {
-      const int e = t + (i0 + i) * kMlpThreads;
-      W[lidx(e / K, e % K, SWl)] = (__bf16)v[i];
+    for (int i = 0; i < kBatch; ++i) {
+      const int e = 2 * (t + (i0 + i) * kMlpThreads);
+      bf16x2 h;
+      h[0] = (__bf16)v[i][0];
+      h[1] = (__bf16)v[i][1];
+      *(bf16x2*)&W[lidx(e / K, e % K, SWl)] = h;
     }
   }
 }
@@ -274,9 +281,10 @@ __device__ __forceinline__ void load_layer_weights(const Smem<U, H>& S, const fl
 // Copy the FP32 parameters of one network into the workgroup's BF16 / FP32 LDS copies.
 template <int U, int H>
 __device__ void load_weights(const Smem<U, H>& S, const float* P, const MlpLayout& L) {
-  load_layer_weights<U, H, 1>(S, P + L.w_off(1), opaque_tid());
-  if constexpr (H >= 2) load_layer_weights<U, H, 2>(S, P + L.w_off(2), opaque_tid());
-  if constexpr (H >= 3) load_layer_weights<U, H, 3>(S, P + L.w_off(3), opaque_tid());
+  const int t = opaque_tid();
+  load_layer_weights<U, H, 1>(S, P + L.w_off(1), t);
+  if constexpr (H >= 2) load_layer_weights<U, H, 2>(S, P + L.w_off(2), t);
+  if constexpr (H >= 3) load_layer_weights<U, H, 3>(S, P + L.w_off(3), t);
   for (int l = 1; l <= H; ++l)
     for (int e = opaque_tid(); e < U; e += kMlpThreads) S.bias(l)[e] = P[L.b_off(l) + e];
   for (int e = opaque_tid(); e < U; e += kMlpThreads) S.wout()[e] = P[L.wout_off() + e];

@@ -195,6 +195,8 @@ int cva_regress_fit(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, i
   int rc = fill_args(c, n_reg, dates, n_dates_total, M, n_feat, a);
   if (rc) return rc;
   if (!X_dev || !Y_dev || !model_dev) return fail(HSIM_EINVAL, "X, Y and model must not be NULL");
+  if (!plain(c) && ((uintptr_t)model_dev & 7u))
+    return fail(HSIM_EINVAL, "model must be 8-byte aligned (weights are read in pairs)");
   if (plain(c))
     return plain_fit(c, n_reg, dates, M, n_feat, X_dev, Y_dev, W_dev, seed, model_dev, loss_hist_dev, workspace_dev,
                      ws_bytes, (hipStream_t)stream);
@@ -281,6 +283,8 @@ int cva_regress_predict(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* date
   int rc = fill_args(c, n_reg, dates, n_dates_total, M, n_feat, a);
   if (rc) return rc;
   if (!X_dev || !model_dev || !out_dev) return fail(HSIM_EINVAL, "X, model and out must not be NULL");
+  if (!plain(c) && ((uintptr_t)model_dev & 7u))
+    return fail(HSIM_EINVAL, "model must be 8-byte aligned (weights are read in pairs)");
   if (plain(c)) return plain_predict(c, n_reg, dates, M, n_feat, X_dev, model_dev, out_dev, (hipStream_t)stream);
   a.X = (const float*)X_dev;
   a.Y = nullptr;

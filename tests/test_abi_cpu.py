@@ -253,3 +253,19 @@ def test_oversim_chooser_matches_oracle(hs):
         hs.oversim_cost_ratio(1.0, 0.5, 1.0, 64.0)       # the larger n_b ran faster: P < 0
     with pytest.raises(hs.HsimError):
         hs.oversim_choose(mom, -1.0, 1e9)
+
+
+def test_regression_rejects_misaligned_model(hs, cpu_only):
+    """The BF16 kernel reads a network's weights in 8-byte pairs: a model pointer that is not
+    8-byte aligned is refused before any launch (the FP32 / FP64 form takes any alignment)."""
+    mlp = wl.MLPConfig(hidden=2, width=32, epochs=1, batch=64)
+    cfg = hs.mlp_cfg(mlp, 3, 128)
+    dates = np.array([1], dtype=np.int32)
+    ok = ctypes.c_void_p(4096)
+    odd = ctypes.c_void_p(4096 + 4)      # never dereferenced: validation fails first
+    L = hs.lib()
+    rc = L.cva_regress_fit(ctypes.byref(cfg), 1, dates.ctypes.data_as(hs._c_i32p), 3, 128, 3, ok, ok, None, 0,
+                           odd, None, ok, 1 << 20, None)
+    assert rc == -1 and "8-byte" in L.hsim_last_error().decode()
+    rc = L.cva_regress_predict(ctypes.byref(cfg), 1, dates.ctypes.data_as(hs._c_i32p), 3, 128, 3, ok, odd, ok, None)
+    assert rc == -1 and "8-byte" in L.hsim_last_error().decode()
