@@ -3,7 +3,8 @@
 One step = one pass of the whole hot path (one CVA-with-sensitivities solve) on the
 ten-currency / nine-FX / eight-counterparty / 500-swap workload (100 pricing dates x 25 Euler
 sub-steps over 10y, FP32 simulation with FP64 integrals):
-  1. M = 2^17 outer paths + pricing -> n_b = 128 inner default draws -> targets and CVA_0;
+  1. M = 2^17 outer paths + pricing -> n_b = 128 inner default draws -> targets and CVA_0, in
+     one launch (hsim_fused_keep, which also keeps the forward states of the first 2^16 paths);
   2. NN^+ regression of the targets at all 100 dates in one persistent launch (3 x 128 ReLU,
      29 inputs, BF16 on the matrix cores, batch 8192, 50 epochs);
   3. CVA_0 sensitivities to the 90 model inputs by the tangent/adjoint sweeps on the first
@@ -12,9 +13,10 @@ The metric is outer x inner path-steps per second of the whole step:
 M * n_b * n_dates / (seconds per step).
 
 Also reported: per-stage times (HIP events on the launch stream), the roofline of the
-dominant kernel (and of the simulation kernel), the plain-FP32 comparison solve (same
-simulation, sequential per-date FP32 regression in plain PyTorch, sensitivities by central
-finite differences with common random numbers), the FP64 oracle on the host cores, and,
+dominant kernel (and of the simulation kernel), the same simulation as three separate launches
+(outside the timed step; same targets bit for bit), the plain-FP32 comparison solve (simulation
+with FP32 integrals, BaseAlg per date with the library's FP32 regression, sensitivities by
+central finite differences with common random numbers), the FP64 oracle on the host cores, and,
 outside the timed step, the twin and nested Monte Carlo errors of the fitted network at
 t = 5y on out-of-sample paths (branched re-simulation).
 
@@ -384,7 +386,8 @@ def main():
     ap.add_argument("--sweep-M", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (scale of the FETCH/WRITE counters)")
-    ap.add_argument("--no-fused", action="store_true", help="skip the one-launch simulation line")
+    ap.add_argument("--no-fused", action="store_true",
+                    help="skip the line of the simulation as three separate launches")
     ap.add_argument("--no-validation", action="store_true",
                     help="skip the twin / nested Monte Carlo check of the fitted network")
     args = ap.parse_args()
@@ -460,32 +463,31 @@ def main():
     dates_c = np.asarray(dates, dtype=np.int32)
     adj = hsim.Adjoint(wa, fixed=fixed)
 
-    stages = ["outer", "inner", "targets"] + ([] if args.sim_only else ["regression", "adjoint"])
+    # the simulation of the step: outer paths, inner draws, targets and CVA_0 in one launch
+    # (hsim_fused_keep), which also keeps the forward states I, Lambda, D of the first 2^16 paths
+    # for the sensitivities; features and targets go to the regression
+    fs = hsim.FusedSolver(w, precision=prec, fixed=fixed)
+    n_keep = wa.M
+
+    stages = ["simulation"] + ([] if args.sim_only else ["regression", "adjoint"])
 
     def step(ev=None):
         def mark(k):
             if ev is not None:
                 ev[k].record(stream)
         mark(0)
-        hsim.check(L.hsim_outer_paths(by(km.struct), by(kp.struct), by(g), w.seed, 0, M, prec, fm,
-                                      P(feats), P(I), P(Lam), P(D), None, hsim._stream()))
+        fs.run_keep(n_keep, I, Lam, D)
         mark(1)
-        hsim.check(L.hsim_inner_defaults(by(g), C, w.seed, 0, M, w.n_b, None, 64, P(Lam), P(cnt),
-                                         None, 0, hsim._stream()))
-        mark(2)
-        hsim.check(L.hsim_targets_cva(by(g), C, M, w.n_b, None, 64, prec, P(I), P(D), P(cnt),
-                                      P(T), P(cva0), P(ws), wsb, hsim._stream()))
-        mark(3)
         if args.sim_only:
             return
         hsim.check(L.cva_regress_fit(by(cfg), len(dates), dates_c.ctypes.data_as(hsim._c_i32p), n1, M, d,
-                                     P(feats), P(T), None, w.seed, P(model), None, P(mws_t), mws,
+                                     P(fs.features), P(fs.T), None, w.seed, P(model), None, P(mws_t), mws,
                                      hsim._stream()))
-        mark(4)
+        mark(2)
         # sensitivities on the first 2^16 of the paths just simulated (same market and seed): the
         # adjoint reads their forward states instead of simulating them again
-        adj.from_forward(feats, I, Lam, D)
-        mark(5)
+        adj.from_forward(fs.features, I, Lam, D)
+        mark(3)
 
     for _ in range(args.warmup):
         step()
@@ -509,11 +511,13 @@ def main():
     path_steps = M * w.n_b * w.grid.n_dates
     value = path_steps / (ms_step / 1e3)
     ops = outer_ops_per_path(w)["total"] * M
-    outer_roof = {"bound": "alu", "kernel": "outer_kernel<float,10,8>",
-                  "achieved": ops / (stage_ms["outer"] / 1e3) / 1e12,
+    # the outer-path operations of the one-launch simulation (its inner draws and targets, 10 %
+    # of the launch, are not counted: the fraction is a lower bound)
+    outer_roof = {"bound": "alu", "kernel": "fused_kernel<float,10,8> (outer-path operations)",
+                  "achieved": ops / (stage_ms["simulation"] / 1e3) / 1e12,
                   "peak": VALU_PEAK_OPS / 1e12, "unit": "T VALU lane-ops/s",
-                  "frac": ops / (stage_ms["outer"] / 1e3) / VALU_PEAK_OPS, "traffic": None,
-                  "valu_issue_utilization": profiled_value("valu_issue_utilization", "outer_kernel", "sim.hip")}
+                  "frac": ops / (stage_ms["simulation"] / 1e3) / VALU_PEAK_OPS, "traffic": None,
+                  "valu_issue_utilization": profiled_value("valu_issue_utilization", "fused_kernel", "sim.hip")}
     roof = outer_roof
     mlp_roof = None
     if not args.sim_only:
@@ -524,36 +528,47 @@ def main():
                     "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s",
                     "frac": fl / (stage_ms["regression"] / 1e3) / BF16_PEAK,
                     "traffic": profiled_traffic("mlp_train_kernel", "regress.hip")}
-        if stage_ms["regression"] > stage_ms["outer"]:
+        if stage_ms["regression"] > stage_ms["simulation"]:
             roof = mlp_roof
 
     plain = None
     if not args.sim_only and not args.no_plain:
-        cva_fast, grad_fast = adj.from_forward(feats, I, Lam, D)
-        fast = {"T": T, "cva0": cva0.item(), "cfg": cfg, "dates": dates, "model": model,
+        cva_fast, grad_fast = adj.from_forward(fs.features, I, Lam, D)
+        fast = {"T": fs.T, "cva0": fs.cva0.item(), "cfg": cfg, "dates": dates, "model": model,
                 "grad": grad_fast.cpu().numpy().copy(), "solve_s": ms_step / 1e3}
         plain = plain_fp32_solve(hsim, torch, w, wr, wa, fixed, fast)
         print(f"# plain FP32 form: {plain['solve_s']:.2f} s per solve", file=sys.stderr, flush=True)
 
-    fused = None
+    separate = None
     if not args.no_fused:
-        # the one-launch simulation (hsim_fused) on the same workload, outside the timed step:
-        # same features, targets and CVA_0 as the three stages above
-        fs = hsim.FusedSolver(w, precision=prec, fixed=fixed)
-        fs.run()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        # the same simulation as three launches (hsim_outer_paths, hsim_inner_defaults,
+        # hsim_targets_cva) outside the timed step: same targets and CVA_0 bit for bit
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ms = {"outer": [], "inner": [], "targets": []}
         for _ in range(3):
-            fs.run()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        split = stage_ms["outer"] + stage_ms["inner"] + stage_ms["targets"]
-        fused = {"ms": e0.elapsed_time(e1) / 3, "separate_stages_ms": split,
-                 "same_cva0": bool(fs.cva0.item() == cva0.item()),
-                 "same_targets": bool(torch.equal(fs.T, T)),
-                 "path_steps_per_s": path_steps / (e0.elapsed_time(e1) / 3 / 1e3)}
-        del fs
+            e[0].record(stream)
+            hsim.check(L.hsim_outer_paths(by(km.struct), by(kp.struct), by(g), w.seed, 0, M, prec, fm,
+                                          P(feats), P(I), P(Lam), P(D), None, hsim._stream()))
+            e[1].record(stream)
+            hsim.check(L.hsim_inner_defaults(by(g), C, w.seed, 0, M, w.n_b, None, 64, P(Lam), P(cnt),
+                                             None, 0, hsim._stream()))
+            e[2].record(stream)
+            hsim.check(L.hsim_targets_cva(by(g), C, M, w.n_b, None, 64, prec, P(I), P(D), P(cnt),
+                                          P(T), P(cva0), P(ws), wsb, hsim._stream()))
+            e[3].record(stream)
+            torch.cuda.synchronize()
+            for j, k in enumerate(ms):
+                ms[k].append(e[j].elapsed_time(e[j + 1]))
+        stage = {k: float(np.mean(v)) for k, v in ms.items()}
+        separate = {"ms": sum(stage.values()), "stage_ms": stage, "one_launch_ms": stage_ms["simulation"],
+                    "same_cva0": bool(fs.cva0.item() == cva0.item()),
+                    "same_targets": bool(torch.equal(fs.T, T)),
+                    "outer_kernel_roofline": {
+                        "bound": "alu", "kernel": "outer_kernel<float,10,8>",
+                        "achieved": ops / (stage["outer"] / 1e3) / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                        "unit": "T VALU lane-ops/s", "frac": ops / (stage["outer"] / 1e3) / VALU_PEAK_OPS,
+                        "valu_issue_utilization": profiled_value("valu_issue_utilization", "outer_kernel",
+                                                                 "sim.hip")}}
 
     sweep = None
     if not args.sim_only and not args.no_sweep:
@@ -589,9 +604,9 @@ def main():
         "roofline": roof,
         "roofline_simulation": outer_roof,
         "roofline_regression": mlp_roof,
-        "cva0": cva0.item(),
+        "cva0": fs.cva0.item(),
         "plain_fp32": plain,
-        "fused_simulation": fused,
+        "separate_simulation_stages": separate,
         "oversim_sweep": sweep,
         "validation": valid,
         "cpu_baseline": cpu,

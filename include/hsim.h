@@ -272,6 +272,19 @@ int hsim_fused(const hsim_market* market, const hsim_portfolio* book, const hsim
                int precision, int feature_mode, void* features_dev, void* target_dev, double* cva0_dev,
                void* workspace_dev, size_t ws_bytes, void* stream);
 
+/* hsim_fused that also writes the forward states of the first n_keep paths (0 <= n_keep <= M)
+ * date-major, as hsim_outer_paths writes them: I_dev [n+1][M], Lambda_dev [n+1][C][M] (double)
+ * and D_dev [n+1][C][M] (float if FP32 else double), columns 0 .. n_keep - 1 written, the rest
+ * untouched; with the features they are the input of cva_adjoint_forward (ld = M) for those
+ * paths, so a solve needs no separate forward pass for its sensitivities.  The values equal
+ * hsim_outer_paths' bit for bit.  n_keep = 0: hsim_fused (the three pointers may be NULL);
+ * n_keep > 0 with a NULL pointer, or n_keep out of range: HSIM_EINVAL. */
+int hsim_fused_keep(const hsim_market* market, const hsim_portfolio* book, const hsim_grid* grid, uint64_t seed,
+                    int64_t path_begin, int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
+                    int precision, int feature_mode, void* features_dev, void* target_dev, double* cva0_dev,
+                    int64_t n_keep, double* I_dev, double* Lambda_dev, void* D_dev, void* workspace_dev,
+                    size_t ws_bytes, void* stream);
+
 /* Pilot moments of the oversimulation chooser (Section 3.3, Proposition p:heurisN).  For
  * every date i and path k of T1_dev / T2_dev [n+1][M] (the n_b = 1 and n_b = 2 targets of
  * one seed, float if FP32 else double; with the common random numbers of

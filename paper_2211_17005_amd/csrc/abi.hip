@@ -695,6 +695,16 @@ int hsim_fused(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g
                int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths, int precision,
                int feature_mode, void* features_dev, void* target_dev, double* cva0_dev, void* workspace_dev,
                size_t ws_bytes, void* stream) {
+  return hsim_fused_keep(m, p, g, seed, path_begin, M, n_b, n_b_per_block, block_paths, precision, feature_mode,
+                         features_dev, target_dev, cva0_dev, 0, nullptr, nullptr, nullptr, workspace_dev, ws_bytes,
+                         stream);
+}
+
+int hsim_fused_keep(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g, uint64_t seed,
+                    int64_t path_begin, int64_t M, int32_t n_b, const int32_t* n_b_per_block, int32_t block_paths,
+                    int precision, int feature_mode, void* features_dev, void* target_dev, double* cva0_dev,
+                    int64_t n_keep, double* I_dev, double* Lambda_dev, void* D_dev, void* workspace_dev,
+                    size_t ws_bytes, void* stream) {
   int rc = check_precision(precision);
   if (rc) return rc;
   if ((rc = check_market(m))) return rc;
@@ -702,6 +712,9 @@ int hsim_fused(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g
   if ((rc = check_paths(path_begin, M))) return rc;
   if ((rc = check_nb(n_b, n_b_per_block, block_paths))) return rc;
   if (!target_dev || !cva0_dev) return fail(HSIM_EINVAL, "target and cva0 must not be NULL");
+  if (n_keep < 0 || n_keep > M) return fail(HSIM_EINVAL, "n_keep=%lld out of [0, M=%lld]", (long long)n_keep, (long long)M);
+  if (n_keep > 0 && (!I_dev || !Lambda_dev || !D_dev))
+    return fail(HSIM_EINVAL, "I, Lambda and D must not be NULL when n_keep > 0");
   const size_t rs = precision == HSIM_FP64 ? sizeof(double) : sizeof(float);
   if (fused_lds_bytes(g->n_dates, m->n_cpty, rs) > kFusedMaxLds)
     return fail(HSIM_ERANGE, "n_dates x n_cpty too large for the fused kernel's LDS (%zu > %zu bytes): use "
@@ -724,6 +737,10 @@ int hsim_fused(const hsim_market* m, const hsim_portfolio* p, const hsim_grid* g
   w += align256(Mz * sizeof(double));
   double* partial = (double*)w;
   f.T = target_dev;
+  f.n_keep = n_keep;
+  f.I_keep = I_dev;
+  f.Lam_keep = Lambda_dev;
+  f.D_keep = D_dev;
   auto run = [&](auto tag) -> int {
     using Real = decltype(tag);
     SimArgs<Real> a;

@@ -608,6 +608,16 @@ __device__ __forceinline__ void fused_emit(const SimArgs<Real>& a, const FusedAr
     Dv[row + c] = exposure<Real, double>(a, beta, mtm[c], c);
   }
   f.Iv[kl * n1 + i] = st.I;
+  if (kl < f.n_keep) {                       // the date-major states of hsim_outer_paths
+    const int64_t M = a.M;
+    f.I_keep[(int64_t)i * M + kl] = st.I;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t o = ((int64_t)i * NC + c) * M + kl;
+      f.Lam_keep[o] = st.Lam[c];
+      ((Real*)f.D_keep)[o] = Dv[row + c];
+    }
+  }
   emit_features<Real, NE, NC, double>(a, st, i, kl);
 }
 

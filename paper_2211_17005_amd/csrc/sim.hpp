@@ -115,6 +115,12 @@ struct FusedArgs {
   double* Iv;                        // [M][n+1] discount integrals
   void* T;                           // [n+1][M] targets (Real)
   double* T0;                        // [M] T_0 in FP64 (the CVA_0 reduction's input)
+  // forward states of the paths kl < n_keep, date-major with leading dimension M (as
+  // hsim_outer_paths writes them), for a later adjoint; n_keep = 0: none
+  int64_t n_keep;
+  double* I_keep;                    // [n+1][M]
+  double* Lam_keep;                  // [n+1][C][M]
+  void* D_keep;                      // [n+1][C][M] (Real)
 };
 
 // LDS of one fused workgroup: thresholds and histogram [n+1][C] uint32 each, then (8-byte

@@ -97,6 +97,8 @@ def lib():
         "hsim_workspace_bytes": (sz, [ctypes.c_int, M_, G_, i64, ctypes.c_int]),
         "hsim_fused": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i32, vp, i32, ctypes.c_int, ctypes.c_int,
                                       vp, vp, vp, vp, sz, vp]),
+        "hsim_fused_keep": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, i32, vp, i32, ctypes.c_int, ctypes.c_int,
+                                           vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]),
         "hsim_n_params": (ctypes.c_int, [M_]),
         "cva_adjoint": (ctypes.c_int, [M_, P_, G_, u64, i64, i64, vp, vp, vp, sz, vp]),
         "cva_regress_record_floats": (ctypes.c_int, [ctypes.POINTER(MlpCfg)]),
@@ -542,6 +544,21 @@ class FusedSolver(Solver):
             self.w.seed, path_begin, self.M, self.nb, _dptr(self.nbt), self.bp, self.precision,
             self.fm, _dptr(self.features if want_features else None), _dptr(self.T),
             _dptr(self.cva0), _dptr(self.ws), self.wsb, _stream()))
+        return self.features, self.T, self.cva0
+
+    def run_keep(self, n_keep: int, I, Lam, D, path_begin: int = 0, want_features: bool = True):
+        """hsim_fused_keep: run() plus the forward states of the first n_keep paths into I [n+1][M],
+        Lam [n+1][C][M] (float64) and D [n+1][C][M] (the solver's real type)."""
+        import torch
+        n1, C = self.w.grid.n_dates + 1, self.market.n_cpty
+        _expect(I, torch.float64, (n1, self.M), "I")
+        _expect(Lam, torch.float64, (n1, C, self.M), "Lambda")
+        _expect(D, _real(self.precision), (n1, C, self.M), "D")
+        check(lib().hsim_fused_keep(
+            ctypes.byref(self.km.struct), ctypes.byref(self.kp.struct), ctypes.byref(self.g),
+            self.w.seed, path_begin, self.M, self.nb, _dptr(self.nbt), self.bp, self.precision,
+            self.fm, _dptr(self.features if want_features else None), _dptr(self.T),
+            _dptr(self.cva0), int(n_keep), _dptr(I), _dptr(Lam), _dptr(D), _dptr(self.ws), self.wsb, _stream()))
         return self.features, self.T, self.cva0
 
 

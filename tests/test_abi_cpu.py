@@ -150,6 +150,12 @@ def test_one_launch_rejects_bad_arguments(hs, cpu_only):
                                                     dummy, dummy, dummy, ws, None)
     assert call(g, 1, need - 1) == -3
     assert call(g, hs.HSIM_FP32_PLAIN, need) == -1
+    keep = lambda n_keep, ptr: hs.lib().hsim_fused_keep(ctypes.byref(km.struct), ctypes.byref(kp.struct),
+                                                       ctypes.byref(g), 0, 0, w.M, 8, None, 64, 1, 0, None,
+                                                       dummy, dummy, n_keep, ptr, ptr, ptr, dummy, need, None)
+    assert keep(w.M + 1, dummy) == -1 and b"n_keep" in hs.lib().hsim_last_error()
+    assert keep(-1, dummy) == -1
+    assert keep(5, None) == -1 and b"NULL" in hs.lib().hsim_last_error()
     big = hs.grid_struct(wl.Grid(8.0, 512, 5))        # 513 dates x 16 counterparties: 104 KiB of LDS
     m16 = hs.market_struct(wl.small_multi(n_cpty=16).market)
     need16 = hs.lib().hsim_workspace_bytes(hs.OP_FUSED_LAUNCH, ctypes.byref(m16.struct), ctypes.byref(big), 64, 1)

@@ -128,3 +128,9 @@ def test_adjoint_from_forward_outputs_equals_own_forward(lib, name):
     cva0, grad = adj.from_forward(feats, I, Lam, D)
     print(f"  {name}: CVA_0 {cva0.item():.10g} vs {c_ref.item():.10g}", flush=True)
     assert torch.equal(cva0, c_ref) and torch.equal(grad, g_ref)
+    # the same states kept by the one-launch simulation of the 2M paths (the bench's route)
+    fs = lib.FusedSolver(w.with_(M=2 * w.M), precision=lib.HSIM_FP32)
+    I.fill_(float("nan")); Lam.fill_(float("nan")); D.fill_(float("nan"))
+    f2, _, _ = fs.run_keep(w.M, I, Lam, D)
+    cva0, grad = adj.from_forward(f2, I, Lam, D)
+    assert torch.equal(cva0, c_ref) and torch.equal(grad, g_ref)

@@ -188,6 +188,31 @@ def test_one_launch_equals_separate_stages(lib, name, precision):
     assert torch.equal(f1, f2) and torch.equal(T1, T2) and torch.equal(c1, c2)
 
 
+@pytest.mark.parametrize("name", ["small_multi", "ten_currencies"])
+def test_one_launch_keeps_forward_states(lib, name):
+    """hsim_fused_keep writes I, Lambda and D of the first n_keep paths (ragged, not a whole tile)
+    date-major exactly as hsim_outer_paths does, leaves the other columns alone, and changes
+    nothing else of the one-launch results."""
+    import torch
+    w = dict(FUSED_CASES)[name]()
+    M, n1, C = w.M, w.grid.n_dates + 1, w.market.n_cpty
+    n_keep = M // 2 + 3
+    out = lib.outer_paths(w, precision=1, want_features=False)
+    fs = lib.FusedSolver(w, precision=1)
+    f1, T1, c1 = [x.clone() for x in fs.run()]
+    I = torch.full((n1, M), float("nan"), dtype=torch.float64, device="cuda")
+    Lam = torch.full((n1, C, M), float("nan"), dtype=torch.float64, device="cuda")
+    D = torch.full((n1, C, M), float("nan"), dtype=torch.float32, device="cuda")
+    f2, T2, c2 = fs.run_keep(n_keep, I, Lam, D)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2) and torch.equal(T1, T2) and torch.equal(c1, c2)
+    assert torch.equal(I[:, :n_keep], out["I"][:, :n_keep])
+    assert torch.equal(Lam[..., :n_keep], out["Lam"][..., :n_keep])
+    assert torch.equal(D[..., :n_keep], out["D"][..., :n_keep])
+    assert bool(torch.isnan(I[:, n_keep:]).all() and torch.isnan(Lam[..., n_keep:]).all()
+                and torch.isnan(D[..., n_keep:]).all())
+
+
 def test_one_launch_uneven_nb_and_path_offset(lib):
     """Uneven n_b per block of 64 paths and a path range that does not start at 0."""
     import torch
