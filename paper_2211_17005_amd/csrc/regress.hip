@@ -368,6 +368,14 @@ __device__ __forceinline__ RowTarget store_chunk(const Smem<U, H>& S, const Chun
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
+// ReLU of rounded values on the packed 16-bit words: a BF16 word is below zero exactly when its
+// sign bit is set, i.e. when it is negative as a 16-bit integer, so max(word, 0) over integers is
+// the ReLU (rounding to nearest commutes with it; -0 becomes +0).
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x4 relu_bf16(const bf16x4& h) {
+  return __builtin_bit_cast(bf16x4, __builtin_elementwise_max(__builtin_bit_cast(s16x4, h), (s16x4)0));
+}
+
 // Bit v set where h[v] != 0 (for h >= 0: where h[v] > 0), tested on the packed 16-bit words.
 __device__ __forceinline__ uint32_t nonzero_bits(const bf16x4& h) {
   typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -395,11 +403,16 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __
   const __bf16* W = S.W(L);
   const __bf16* Ain = L == 1 ? a0 : S.A(L - 1);
   __bf16* Aout = S.A(L);
+  // the accumulators start from the bias of their output units (the 16 x 16 tile layout puts
+  // units 4 (lane / 16) .. + 3 of the tile in a lane), so the epilogue adds nothing
+  const float* b = S.bias(L);
   f32x4 acc[B::BO][B::BR];
 #pragma unroll
-  for (int x = 0; x < B::BO; ++x)
+  for (int x = 0; x < B::BO; ++x) {
+    const f32x4 bb = *(const f32x4*)&b[16 * (ob * B::BO + x) + 4 * (lane / 16)];
 #pragma unroll
-    for (int y = 0; y < B::BR; ++y) acc[x][y] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int y = 0; y < B::BR; ++y) acc[x][y] = bb;
+  }
 #pragma unroll
   for (int k0 = 0; k0 < K; k0 += 32) {
     bf16x8 av[B::BO], bv[B::BR];
@@ -412,7 +425,6 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __
 #pragma unroll
       for (int y = 0; y < B::BR; ++y) acc[x][y] = mfma16(av[x], bv[y], acc[x][y]);
   }
-  const float* b = S.bias(L);
   uint32_t mask = 0u;
   float pf[B::BR];                      // last layer: this lane's part of f = A_H w_out
 #pragma unroll
@@ -420,17 +432,17 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __
 #pragma unroll
   for (int x = 0; x < B::BO; ++x) {
     const int out0 = 16 * (ob * B::BO + x) + 4 * (lane / 16);
-    const f32x4 bb = *(const f32x4*)&b[out0];
     f32x4 wo = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (L == H) wo = *(const f32x4*)&S.wout()[out0];
 #pragma unroll
     for (int y = 0; y < B::BR; ++y) {
       bf16x4 h;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        h[v] = (__bf16)fmaxf(acc[x][y][v] + bb[v], 0.0f);
-        if constexpr (L == H) pf[y] += (float)h[v] * wo[v];
-      }
+      for (int v = 0; v < 4; ++v) h[v] = (__bf16)acc[x][y][v];
+      h = relu_bf16(h);
+      if constexpr (L == H)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pf[y] += (float)h[v] * wo[v];
       mask |= nonzero_bits(h) << (4 * (x * B::BR + y));
       if (kKeep || L < H) *tile_strip(Aout, oo, SW, rb * B::BR + y, ob * B::BO + x) = h;
     }
