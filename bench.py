@@ -381,7 +381,8 @@ def main():
     ap.add_argument("--cpu-sim-paths", type=int, default=1280, help="oracle paths per process")
     ap.add_argument("--cpu-rows", type=int, default=65536, help="oracle regression rows per process")
     ap.add_argument("--cpu-sens-paths", type=int, default=384, help="oracle CVA_0 paths per process")
-    ap.add_argument("--team", type=int, default=0, help="workgroups per date (0: autotuned)")
+    ap.add_argument("--team", type=int, default=0, help="workgroups per date (0: autotuned with the tiling)")
+    ap.add_argument("--tile", type=int, default=0, help="wave tiling of the regression kernels with --team")
     ap.add_argument("--no-sweep", action="store_true", help="skip the uneven-n_b sweep line")
     ap.add_argument("--sweep-M", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -455,7 +456,10 @@ def main():
                                   P(T), P(cva0), P(ws), wsb, hsim._stream()))
     if not args.sim_only:
         from paper_2211_17005_amd import autotune
-        cfg.team = args.team if args.team > 0 else autotune.regression_team(cfg, dates, feats, T, seed=w.seed)
+        if args.team > 0:
+            cfg.team, cfg.tile = args.team, args.tile
+        else:
+            cfg.team, cfg.tile = autotune.regression_launch(cfg, dates, feats, T, seed=w.seed)
     rec = hsim.record_floats(cfg)
     model = torch.zeros((len(dates), rec), dtype=torch.float32, device="cuda")
     mws = L.cva_regress_workspace_bytes(by(cfg), len(dates), M)
@@ -596,6 +600,7 @@ def main():
                    "n_swaps": w.portfolio.n_swaps, "n_dates": w.grid.n_dates,
                    "n_sub": w.grid.n_sub, "M": M, "n_b": w.n_b, "stages": stages,
                    "regression": {"dates": len(dates), "hidden": wr.mlp.hidden, "team": int(cfg.team),
+                                  "tile": int(cfg.tile),
                                   "width": wr.mlp.width, "inputs": d, "batch": wr.mlp.batch,
                                   "epochs": wr.mlp.epochs},
                    "sensitivities": {"M": wa.M, "inputs": int(hsim.n_params(wa.market))}},

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define HSIM_ABI_VERSION 2
+#define HSIM_ABI_VERSION 3
 
 enum hsim_status {
   HSIM_OK = 0,
@@ -396,6 +396,13 @@ typedef struct {
                          after another (team ignored), any width 1..128 with 1..3 hidden layers;
                          X, Y, W, the model record and the loss history are then float (FP32) or
                          double (FP64).  Same initial draw, readings and record layout in all three */
+  int32_t tile;       /* HSIM_REG_BF16: the kernels' wave tiling (0, 1, 2): the block of 16 x 16
+                         output tiles each of the 8 waves owns at width 128 in the forward and
+                         back-propagation products, 0: 2 units x 2 rows, 1: 4 x 1, 2: 1 x 4 (at
+                         width 64: 2 x 1, 2 x 1, 1 x 2), and in the weight-gradient products 2 x 4,
+                         4 x 2, 1 x 8 (out x in).  Picked by the autotuner; results depend on it only
+                         through the summation order of the output unit's partial sums.  Ignored
+                         (must be 0) by the FP32 / FP64 form */
 } cva_mlp_cfg;
 
 enum { HSIM_REG_BF16 = 0, HSIM_REG_FP32 = 1, HSIM_REG_FP64 = 2 };

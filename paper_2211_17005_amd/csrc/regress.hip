@@ -21,12 +21,28 @@
 // layers frozen and mu fixed, then pos = 1; after every epoch the full-sample pos = 1 loss is
 // evaluated and the best parameters are kept.  Inputs are standardised per date and targets
 // divided by their root mean square.
+//
+// Wave tiling variants (the autotuner's tile shapes): this file is compiled once per variant
+// HSIM_MLP_TILE (0: the default; regress_tile1.hip, regress_tile2.hip), each into a namespace
+// of its own, and the C ABI dispatches on cva_mlp_cfg.tile.  A variant changes the block of
+// output tiles a wave owns in the forward and back-propagation products (out x row tiles) and in
+// the weight-gradient products (out x in tiles); the arithmetic of each tile is the same.
 #include <hip/hip_runtime.h>
 
 #include "philox.hpp"
 #include "regress.hpp"
 
+#ifndef HSIM_MLP_TILE
+#define HSIM_MLP_TILE 0
+#endif
+#define HSIM_MLP_NS_CAT(t) tile##t
+#define HSIM_MLP_NS(t) HSIM_MLP_NS_CAT(t)
+
 namespace hsim {
+namespace HSIM_MLP_NS(HSIM_MLP_TILE) {
+
+constexpr int kTile = HSIM_MLP_TILE;
+static_assert(kTile >= 0 && kTile < kMlpTiles, "tile variant");
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -225,8 +241,9 @@ struct Smem {
 template <int U>
 struct Blk {
   static constexpr int NT = U / 16, RT = kMlpRows / 16;
-  static constexpr int BO = U >= 64 ? 2 : 1;
-  static constexpr int BR = U >= 128 ? 2 : 1;
+  // variant 0: 2 x 2 tiles at 128 units; 1: 4 x 1; 2: 1 x 4
+  static constexpr int BO = kTile == 0 ? (U >= 64 ? 2 : 1) : kTile == 1 ? (U >= 128 ? 4 : U >= 64 ? 2 : 1) : 1;
+  static constexpr int BR = kTile == 0 ? (U >= 128 ? 2 : 1) : kTile == 1 ? 1 : (U >= 128 ? 4 : U >= 64 ? 2 : 1);
   static constexpr int NOB = NT / BO;
   static_assert(NOB * (RT / BR) == kMlpWaves, "one block per wave");
 };
@@ -245,7 +262,7 @@ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 template <int U, int L>
 struct DwMap {
   static constexpr int NT = U / 16, KT = dw_kt(U, L), TW = dw_tw(U, L);
-  static constexpr int BI = cmin(cmin(KT, TW), 4);
+  static constexpr int BI = cmin(cmin(KT, TW), kTile == 0 ? 4 : kTile == 1 ? 2 : KT);
   static constexpr int BO = TW / BI;
   static constexpr int NIB = KT / BI, NOB = NT / BO;
   static_assert(BO * BI == TW && NIB * NOB * TW == NT * KT && NIB * NOB <= kMlpWaves, "tiling");
@@ -1554,4 +1571,5 @@ hipError_t launch_mlp_predict(const MlpArgs& a, float* out, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+}  // namespace tile<HSIM_MLP_TILE>
 }  // namespace hsim

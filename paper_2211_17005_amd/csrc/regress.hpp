@@ -10,6 +10,7 @@ constexpr int kMlpThreads = 512;     // 8 waves per workgroup; a team of workgro
 constexpr int kMlpWaves = kMlpThreads / 64;
 constexpr int kMlpRows = 64;         // rows of a chunk staged in LDS
 constexpr int kMlpDin = 32;          // input width, padded to one MFMA K step
+constexpr int kMlpTiles = 3;         // wave tiling variants of the kernels
 constexpr int kMaxRegDates = 512;
 constexpr int kTeamSpinLimit = 1 << 22;  // default polls before a bounded wait gives up (several seconds)
 constexpr double kRefitGuard = 1e-12; // refit: a Cholesky pivot at or below this times its diagonal drops the column
@@ -65,6 +66,7 @@ struct MlpArgs {
   int32_t G;                      // workgroups per team (one team trains one date at a time)
   int32_t n_teams;
   int32_t use_init;               // 1: start from `model` (warm start), 0: from the Philox draw
+  int32_t tile;                   // wave tiling variant, 0 .. kMlpTiles - 1 (predictions: any)
   // Loss helpers (all dates trained at once): the full-sample loss of every epoch is computed by
   // workgroups without a team (and by teams once they are done) from per-epoch parameter
   // snapshots; the best epoch is chosen when a date's last loss is in.  snaps null: the teams
@@ -78,12 +80,33 @@ struct MlpArgs {
   int32_t dates[kMaxRegDates];
 };
 
-hipError_t launch_mlp_stats(const MlpArgs& a, hipStream_t s);
-// Teams that fit on the device at once for team size G (all workgroups of a launch are resident).
-int mlp_max_teams(int U, int H, int G);
+// The kernels of each wave tiling variant (regress.hip compiled once per variant).
+#define HSIM_MLP_TILE_DECL(ns)                                                                  \
+  namespace ns {                                                                                \
+  hipError_t launch_mlp_stats(const MlpArgs& a, hipStream_t s);                                 \
+  int mlp_max_teams(int U, int H, int G);                                                       \
+  hipError_t launch_mlp_train(const MlpArgs& a, hipStream_t s);                                 \
+  hipError_t launch_mlp_predict(const MlpArgs& a, float* out, hipStream_t s);                   \
+  bool mlp_supported(int U, int H);                                                             \
+  }
+HSIM_MLP_TILE_DECL(tile0)
+HSIM_MLP_TILE_DECL(tile1)
+HSIM_MLP_TILE_DECL(tile2)
+#undef HSIM_MLP_TILE_DECL
+
+inline hipError_t launch_mlp_stats(const MlpArgs& a, hipStream_t s) { return tile0::launch_mlp_stats(a, s); }
+// Teams that fit on the device at once for team size G (all workgroups of a launch are resident;
+// every variant has the same LDS and registers per workgroup).
+inline int mlp_max_teams(int U, int H, int G) { return tile0::mlp_max_teams(U, H, G); }
 // Launch with a.G, a.n_teams set (a.n_teams <= mlp_max_teams); zeroes the team counters first.
-hipError_t launch_mlp_train(const MlpArgs& a, hipStream_t s);
-hipError_t launch_mlp_predict(const MlpArgs& a, float* out, hipStream_t s);
-bool mlp_supported(int U, int H);
+inline hipError_t launch_mlp_train(const MlpArgs& a, hipStream_t s) {
+  return a.tile == 1 ? tile1::launch_mlp_train(a, s) : a.tile == 2 ? tile2::launch_mlp_train(a, s)
+                                                                  : tile0::launch_mlp_train(a, s);
+}
+inline hipError_t launch_mlp_predict(const MlpArgs& a, float* out, hipStream_t s) {
+  return a.tile == 1 ? tile1::launch_mlp_predict(a, out, s) : a.tile == 2 ? tile2::launch_mlp_predict(a, out, s)
+                                                                          : tile0::launch_mlp_predict(a, out, s);
+}
+inline bool mlp_supported(int U, int H) { return tile0::mlp_supported(U, H); }
 
 }  // namespace hsim

@@ -29,6 +29,8 @@ int check_cfg(const cva_mlp_cfg* c) {
   if (c->d_in < 1 || c->d_in > dmax) return fail(HSIM_ERANGE, "d_in=%d out of [1,%d]", c->d_in, dmax);
   if (c->epochs < 1 || c->batch < 1) return fail(HSIM_EINVAL, "epochs and batch must be >= 1");
   if (c->team < 0 || c->team > 32) return fail(HSIM_ERANGE, "team=%d out of [0,32]", c->team);
+  if (c->tile < 0 || c->tile >= kMlpTiles || (plain(c) && c->tile != 0))
+    return fail(HSIM_ERANGE, "tile=%d out of [0,%d) (0 for the FP32 / FP64 form)", c->tile, kMlpTiles);
   if (!(c->lr >= 0.0) || !(c->beta1 >= 0.0 && c->beta1 < 1.0) || !(c->beta2 >= 0.0 && c->beta2 < 1.0) ||
       !(c->eps > 0.0))
     return fail(HSIM_EINVAL, "bad Adam hyper-parameters");
@@ -59,6 +61,7 @@ int fill_args(const cva_mlp_cfg* c, int32_t n_reg, const int32_t* dates, int32_t
   a.M = M;
   a.n_feat = n_feat;
   a.init_tag = c->init_tag;
+  a.tile = c->tile;
   for (int j = 0; j < n_reg; ++j) a.dates[j] = dates[j];
   return HSIM_OK;
 }

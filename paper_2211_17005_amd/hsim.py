@@ -52,7 +52,7 @@ class MlpCfg(ctypes.Structure):
                 ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
                 ("warm_start", ctypes.c_int32), ("init_tag", ctypes.c_int32),
-                ("team", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+                ("team", ctypes.c_int32), ("dtype", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -570,13 +570,16 @@ def inner_defaults_cva(w, precision: int = HSIM_FP32, path_begin: int = 0, M=Non
 
 # ------------------------------------------------------------------------------- regression
 def mlp_cfg(mlp, d_in: int, M: int, warm_start: bool = False, init_tag: int = 0,
-            team: int = 0, dtype: int = REG_BF16) -> MlpCfg:
+            team: int = 0, dtype: int = REG_BF16, tile: int = 0) -> MlpCfg:
     """C config from a workload's MLP settings (batch = M / n_batches when no batch is given);
-    team = workgroups per date (0: the library's choice); dtype REG_BF16 / REG_FP32 / REG_FP64."""
+    team = workgroups per date (0: the library's choice); dtype REG_BF16 / REG_FP32 / REG_FP64;
+    tile = the BF16 kernels' wave tiling variant (0, 1, 2)."""
     batch = int(mlp.batch) if getattr(mlp, "batch", None) else max(1, M // int(mlp.n_batches))
     return MlpCfg(int(mlp.hidden), int(mlp.width), int(d_in), int(mlp.epochs), batch,
                   float(mlp.lr), float(mlp.beta1), float(mlp.beta2), float(mlp.eps),
-                  1 if warm_start else 0, int(init_tag), int(team), int(dtype))
+                  1 if warm_start else 0, int(init_tag), int(team), int(dtype), int(tile))
+
+MLP_TILES = 3
 
 
 def reg_dtype(cfg: MlpCfg):

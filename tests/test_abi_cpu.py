@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(hs):
 
 
 def test_abi_version(hs):
-    assert hs.abi_version() == 2
+    assert hs.abi_version() == 3
 
 
 def test_par_rates_match_oracle(hs):
@@ -275,3 +275,16 @@ def test_regression_rejects_misaligned_model(hs, cpu_only):
     assert rc == -1 and "8-byte" in L.hsim_last_error().decode()
     rc = L.cva_regress_predict(ctypes.byref(cfg), 1, dates.ctypes.data_as(hs._c_i32p), 3, 128, 3, ok, odd, ok, None)
     assert rc == -1 and "8-byte" in L.hsim_last_error().decode()
+
+
+def test_regression_rejects_unknown_tiling(hs, cpu_only):
+    """cva_mlp_cfg.tile: the BF16 kernels' wave tilings 0 .. 2; the FP32 / FP64 form has only 0."""
+    mlp = wl.MLPConfig(hidden=2, width=32, epochs=1, batch=64)
+    dates = np.array([1], dtype=np.int32)
+    ok = ctypes.c_void_p(4096)
+    L = hs.lib()
+    for tile, dtype in ((3, hs.REG_BF16), (-1, hs.REG_BF16), (1, hs.REG_FP32)):
+        cfg = hs.mlp_cfg(mlp, 3, 128, dtype=dtype, tile=tile)
+        rc = L.cva_regress_fit(ctypes.byref(cfg), 1, dates.ctypes.data_as(hs._c_i32p), 3, 128, 3, ok, ok, None, 0,
+                               ok, None, ok, 1 << 20, None)
+        assert rc == -2 and b"tile" in L.hsim_last_error()

@@ -303,12 +303,12 @@ def test_precision_form_one_step_and_refit_elementwise(lib):
     assert L64 <= Lgpu <= L64 * (1 + 1e-3)
 
 
-def _one_step_case(lib, F, T, date, hidden, width, seed):
+def _one_step_case(lib, F, T, date, hidden, width, seed, tile=0):
     """epochs = 1, batch = M: the fit is one Adam step from the initial draw."""
     import torch
     M, d = F.shape[2], F.shape[1]
     mlp = wl.MLPConfig(hidden=hidden, width=width, epochs=1, batch=M)
-    cfg = lib.mlp_cfg(mlp, d, M, team=1)
+    cfg = lib.mlp_cfg(mlp, d, M, team=1, tile=tile)
     X = torch.as_tensor(F.astype(np.float32), device="cuda")
     Y = torch.as_tensor(T.astype(np.float32), device="cuda")
     model, _, ws = lib.regress_fit(cfg, [date], X, Y, seed=seed)
@@ -322,16 +322,20 @@ def _one_step_case(lib, F, T, date, hidden, width, seed):
     return mlp, p, m, v, g64, E, p0, npy(model)[0].astype(np.float64)
 
 
-@pytest.mark.parametrize("hidden,width,big", [(2, 32, False), (3, 128, True)])
-def test_one_adam_step_matches_oracle_elementwise(lib, data, data_big, hidden, width, big):
+# every wave tiling of the kernels at width 128 (the tilings coincide at width 32)
+SHAPES_TILES = [(2, 32, False, 0), (3, 128, True, 0), (3, 128, True, 1), (3, 128, True, 2)]
+
+
+@pytest.mark.parametrize("hidden,width,big,tile", SHAPES_TILES)
+def test_one_adam_step_matches_oracle_elementwise(lib, data, data_big, hidden, width, big, tile):
     w, r = data_big if big else data
     F, T = f32(r["features"]), f32(r["T"])
-    mlp, p, m, v, g64, E, p0, rec = _one_step_case(lib, F, T, 10, hidden, width, w.seed)
+    mlp, p, m, v, g64, E, p0, rec = _one_step_case(lib, F, T, 10, hidden, width, w.seed, tile)
     b1, b2, lr, eps = mlp.beta1, mlp.beta2, mlp.lr, mlp.eps
     g = m / (1.0 - b1)
     err = np.abs(g - g64)
     worst = np.max(err / np.maximum(E, 1e-300))
-    print(f"  one step {hidden}x{width}: max |g - g64| / bound {worst:.3f}; "
+    print(f"  one step {hidden}x{width} tiling {tile}: max |g - g64| / bound {worst:.3f}; "
           f"median bound / |g64| {np.median(E / np.maximum(np.abs(g64), 1e-300)):.2e}", flush=True)
     assert np.all(err <= E + 1e-7 * np.abs(g64))                       # m: the gradient
     Ev = (1.0 - b2) * (2.0 * np.abs(g64) * E + E * E)
@@ -348,8 +352,8 @@ def test_one_adam_step_matches_oracle_elementwise(lib, data, data_big, hidden, w
           flush=True)
 
 
-@pytest.mark.parametrize("hidden,width,big", [(2, 32, False), (3, 128, True)])
-def test_refit_from_frozen_network_is_least_squares(lib, data, data_big, hidden, width, big):
+@pytest.mark.parametrize("hidden,width,big,tile", SHAPES_TILES)
+def test_refit_from_frozen_network_is_least_squares(lib, data, data_big, hidden, width, big, tile):
     """lr = 0 and 2 epochs: the hidden layers keep the initial draw and the refit at the end of
     epoch 1 is the only change (epoch 2 repeats its loss, the first epoch of least loss is kept).
     The GPU's output layer, evaluated in FP64 on the exact hidden features, reaches the FP64
@@ -361,7 +365,7 @@ def test_refit_from_frozen_network_is_least_squares(lib, data, data_big, hidden,
     M, d = F.shape[2], F.shape[1]
     date = 12
     mlp = wl.MLPConfig(hidden=hidden, width=width, epochs=2, batch=M // 4, lr=0.0)
-    cfg = lib.mlp_cfg(mlp, d, M)
+    cfg = lib.mlp_cfg(mlp, d, M, tile=tile)
     X = torch.as_tensor(F.astype(np.float32), device="cuda")
     Y = torch.as_tensor(T.astype(np.float32), device="cuda")
     model, loss, _ = lib.regress_fit(cfg, [date], X, Y, seed=w.seed)
