@@ -473,7 +473,10 @@ int cva_regress_predict(const cva_mlp_cfg* cfg, int32_t n_reg, const int32_t* da
  * CIR scheme, market parameters by a reverse sweep of the Vasicek / log-FX scheme that re-draws
  * the normals and inverts each Euler sub-step from the state stored at the next pricing date.
  * cva0_dev: one double; grad_dev: [hsim_n_params] doubles (device), or NULL for CVA_0 alone (the
- * reverse sweep is skipped).  Workspace:
+ * reverse sweep is skipped).  With a gradient the credit sweep runs on a second stream of the
+ * library's (one per device, default priority) forked from and joined back into `stream` by
+ * events, beside the market sweep; results are ordered on `stream` as for any other call.
+ * Workspace:
  * hsim_workspace_bytes(HSIM_OP_ADJOINT, ...).
  * ------------------------------------------------------------------------------------------ */
 int hsim_n_params(const hsim_market* market);

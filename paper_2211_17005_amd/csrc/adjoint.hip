@@ -19,6 +19,8 @@
 // Per-path gradients go to a [P+1][M] buffer that a fixed-order reduction averages.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "philox.hpp"
 #include "sim.hpp"
 #include "adjoint.hpp"
@@ -423,20 +425,58 @@ __global__ __launch_bounds__(256) void adj_reduce_one(const double* row, int64_t
 
 #define HSIM_ADJ_SHAPES(X) X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 3) X(10, 8)
 
+// A second stream per device (default priority, non-blocking), created once: the credit sweep
+// runs on it beside the market sweep on the caller's stream (the two write disjoint rows of the
+// per-path buffer), forked and joined by events, so the two one-wave-per-SIMD launches share the
+// SIMDs.  Calls on one device share it: concurrent callers serialise their credit sweeps there.
+static hipError_t side_stream(hipStream_t* out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static hipStream_t streams[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev] && (e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking)) != hipSuccess) return e;
+  *out = streams[dev];
+  return hipSuccess;
+}
+
 hipError_t launch_adjoint(const AdjArgs& a, bool with_grad, hipStream_t stream) {
   const dim3 grid((unsigned)((a.sim.M + kOuterBlock - 1) / kOuterBlock));
+  hipStream_t credit_stream = stream;
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipError_t e = hipSuccess;
+  if (with_grad) {
+    if ((e = side_stream(&credit_stream)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&join, hipEventDisableTiming)) != hipSuccess) {
+      hipEventDestroy(fork);
+      return e;
+    }
+    if ((e = hipEventRecord(fork, stream)) == hipSuccess) e = hipStreamWaitEvent(credit_stream, fork, 0);
+  }
   bool done = false;
 #define X(ne, nc)                                                                                  \
-  if (!done && a.sim.n_ccy == ne && a.sim.n_cpty == nc) {                                          \
-    hipLaunchKernelGGL((credit_kernel<ne, nc>), grid, dim3(kOuterBlock), 0, stream, a);            \
+  if (e == hipSuccess && !done && a.sim.n_ccy == ne && a.sim.n_cpty == nc) {                      \
+    hipLaunchKernelGGL((credit_kernel<ne, nc>), grid, dim3(kOuterBlock), 0, credit_stream, a);     \
     if (with_grad)                                                                                 \
       hipLaunchKernelGGL((market_adjoint_kernel<ne, nc>), grid, dim3(kOuterBlock), 0, stream, a);  \
     done = true;                                                                                   \
   }
   HSIM_ADJ_SHAPES(X)
 #undef X
-  if (!done) return hipErrorInvalidValue;
-  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !done) e = hipErrorInvalidValue;
+  if (e == hipSuccess) e = hipGetLastError();
+  if (with_grad) {
+    // join even after a failed launch, so the caller's stream never runs ahead of the side one
+    const hipError_t j = hipEventRecord(join, credit_stream);
+    const hipError_t w = j == hipSuccess ? hipStreamWaitEvent(stream, join, 0) : j;
+    hipEventDestroy(fork);
+    hipEventDestroy(join);
+    if (e == hipSuccess) e = w;
+  }
   if (e != hipSuccess) return e;
   if (with_grad)
     hipLaunchKernelGGL(adj_reduce, dim3(a.par.n_params + 1), dim3(256), 0, stream, a.grad_path, a.sim.M,
