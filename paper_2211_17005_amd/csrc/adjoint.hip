@@ -330,7 +330,11 @@ void market_adjoint_kernel(const AdjArgs a) {
           const int f = 4 * gcall + t;
           if (f < DW) {
 #pragma unroll
-            for (int p = f; p < DW; ++p) W[p] += s.chol[p * (p + 1) / 2 + f] * z[t];
+            // rows p >= f of column f; the loop runs over every row so that its trip count is a
+          // constant and it unrolls to constant indices (W stays in registers, the factor is
+          // read at fixed offsets)
+          for (int p = 0; p < DW; ++p)
+            if (p >= f) W[p] += s.chol[p * (p + 1) / 2 + f] * z[t];
           }
         }
       }

@@ -212,7 +212,11 @@ __device__ __forceinline__ void advance(const SimArgs<Real>& a, OuterState<Real,
         const int f = 4 * g + t;
         if (f < DW) {
 #pragma unroll
-          for (int p = f; p < DW; ++p) W[p] += a.chol[p * (p + 1) / 2 + f] * z[t];
+          // rows p >= f of column f; the loop runs over every row so that its trip count is a
+          // constant and it unrolls to constant indices (W stays in registers, the factor is
+          // read at fixed offsets)
+          for (int p = 0; p < DW; ++p)
+            if (p >= f) W[p] += a.chol[p * (p + 1) / 2 + f] * z[t];
         } else if (f < NZ) {
           const int c = f - DW;
           const Real gp = st.g[c] > (Real)0 ? st.g[c] : (Real)0;
