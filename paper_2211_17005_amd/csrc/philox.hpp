@@ -53,12 +53,15 @@ __device__ __forceinline__ Real uniform_of(uint32_t x) {
 }
 
 // Box & Muller (1958): (R cos 2 pi u_b, R sin 2 pi u_b), R = sqrt(-2 log u_a).
+// FP32: the gfx950 transcendental instructions, which need no range reduction here (u_a in
+// [2^-24, 1), u_b in (0, 1)): v_log_f32 is log2, so -2 log u = -2 ln 2 log2 u, and v_sin_f32 /
+// v_cos_f32 take their argument in revolutions, so sin 2 pi u_b is one instruction.  The normals
+// stay within 3e-7 of the FP64 ones (the library functions spend most of their instructions on
+// arguments that cannot occur here).
 __device__ __forceinline__ void box_muller(float ua, float ub, float& z0, float& z1) {
-  const float rad = sqrtf(-2.0f * logf(ua));
-  float s, c;
-  sincospif(2.0f * ub, &s, &c);
-  z0 = rad * c;
-  z1 = rad * s;
+  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+  z0 = rad * __builtin_amdgcn_cosf(ub);
+  z1 = rad * __builtin_amdgcn_sinf(ub);
 }
 
 __device__ __forceinline__ void box_muller(double ua, double ub, double& z0, double& z1) {
