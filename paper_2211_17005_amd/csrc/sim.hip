@@ -61,10 +61,17 @@ __device__ __forceinline__ void reset_only(const SimArgs<Real>& a, OuterState<Re
   for (int e = 0; e < NE; ++e) st.invzc[e] = reset_inv_zc<Real, NE, NC>(a, e, st.r[e]);
 }
 
+// The pricing tables through the scalar cache: read-only for the launch, and every lane of a
+// wave reads the same entry (the indices depend on the date and the currency only).
+template <typename Real>
+using ConstTable = const __attribute__((address_space(4))) Real*;
+
 // Value of the book per counterparty at pricing date i (updates the reset state).
 template <typename Real, int NE, int NC, typename Acc = double>
 __device__ __forceinline__ void price(const SimArgs<Real>& a, OuterState<Real, NE, NC, Acc>& st, int i,
                                       Real mtm[NC]) {
+  const ConstTable<Real> G = (ConstTable<Real>)a.G, CW1 = (ConstTable<Real>)a.CW1,
+                         CW2 = (ConstTable<Real>)a.CW2, W1 = (ConstTable<Real>)a.W1;
   const int n = a.n_dates;
   const int q = a.q;
   const int P2 = a.n_periods + 2;
@@ -82,8 +89,8 @@ __device__ __forceinline__ void price(const SimArgs<Real>& a, OuterState<Real, N
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
     const Real re = st.r[e];
-    const Real* lnA = a.lnA + e * (n + 1);
-    const Real* Bv = a.Bv + e * (n + 1);
+    const ConstTable<Real> lnA = (ConstTable<Real>)a.lnA + e * (n + 1);
+    const ConstTable<Real> Bv = (ConstTable<Real>)a.Bv + e * (n + 1);
     Real F;
     if (i == 0) {
       F = (Real)1;
@@ -100,14 +107,14 @@ __device__ __forceinline__ void price(const SimArgs<Real>& a, OuterState<Real, N
       const int tau = kk * q - i;
       const Real zc = exp_r(lnA[tau] - Bv[tau] * re);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] += zc * a.G[(c * NE + e) * P2 + kk];
+      for (int c = 0; c < NC; ++c) acc[c] += zc * G[(c * NE + e) * P2 + kk];
     }
     const Real fx = (e == 0) ? (Real)1 : exp_r(st.x[e > 0 ? e - 1 : 0]);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int base = (c * NE + e) * P2;
-      Real v = F * a.CW1[base + pmin] - acc[c];
-      if (coupon) v -= a.CW2[base + pmin] + a.W1[base + pnow];
+      Real v = F * CW1[base + pmin] - acc[c];
+      if (coupon) v -= CW2[base + pmin] + W1[base + pnow];
       mtm[c] += fx * v;
     }
     if (reset) st.invzc[e] = reset_inv_zc<Real, NE, NC>(a, e, re);
