@@ -143,10 +143,15 @@ struct MarketAdj {
 // Adjoint of the pricing and of the exposure weights at date i, state (r, x, I) at date i and
 // r at the reset date preceding it.  Adds to the state adjoints, the pending reset adjoints and
 // the parameter adjoints.
+// Tables read through the scalar cache (read-only for the launch; every lane of a wave reads the
+// same entry).
+typedef const __attribute__((address_space(4))) float* ConstF;
+
 template <int NE, int NC>
 __device__ void pricing_adjoint(const AdjArgs& a, int i, int64_t kl, const float* r, const float* x,
                                 double I, const float* rlr, MarketAdj<NE, NC>& ad) {
   const SimArgs<float>& s = a.sim;
+  const ConstF G = (ConstF)s.G, CW1 = (ConstF)s.CW1, CW2 = (ConstF)s.CW2, W1 = (ConstF)s.W1;
   const int n = s.n_dates, q = s.q, P2 = s.n_periods + 2;
   const int64_t M = s.M;
   const bool reset = (i % q) == 0;
@@ -162,8 +167,8 @@ __device__ void pricing_adjoint(const AdjArgs& a, int i, int64_t kl, const float
   float Fv[NE], fxv[NE];
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
-    const float* lnA = s.lnA + e * (n + 1);
-    const float* Bv = s.Bv + e * (n + 1);
+    const ConstF lnA = (ConstF)s.lnA + e * (n + 1);
+    const ConstF Bv = (ConstF)s.Bv + e * (n + 1);
     const float invzc = i == 0 ? 1.0f : expf(-lnA[q] + Bv[q] * rlr[e]);
     float F;
     if (i == 0) F = 1.0f;
@@ -180,15 +185,15 @@ __device__ void pricing_adjoint(const AdjArgs& a, int i, int64_t kl, const float
       const int tau = kk * q - i;
       const float zc = expf(lnA[tau] - Bv[tau] * r[e]);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] += zc * s.G[(c * NE + e) * P2 + kk];
+      for (int c = 0; c < NC; ++c) acc[c] += zc * G[(c * NE + e) * P2 + kk];
     }
     const float fx = e == 0 ? 1.0f : expf(x[e > 0 ? e - 1 : 0]);
     fxv[e] = fx;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int base = (c * NE + e) * P2;
-      float v = F * s.CW1[base + pmin] - acc[c];
-      if (coupon) v -= s.CW2[base + pmin] + s.W1[base + pnow];
+      float v = F * CW1[base + pmin] - acc[c];
+      if (coupon) v -= CW2[base + pmin] + W1[base + pnow];
       mtm[c] += fx * v;
     }
   }
@@ -207,12 +212,12 @@ __device__ void pricing_adjoint(const AdjArgs& a, int i, int64_t kl, const float
   // back through each currency
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
-    const float* lnA = s.lnA + e * (n + 1);
-    const float* Bv = s.Bv + e * (n + 1);
-    const float* dAa = a.dlnA_da + e * (n + 1);
-    const float* dAb = a.dlnA_db + e * (n + 1);
-    const float* dAs = a.dlnA_ds + e * (n + 1);
-    const float* dBa = a.dB_da + e * (n + 1);
+    const ConstF lnA = (ConstF)s.lnA + e * (n + 1);
+    const ConstF Bv = (ConstF)s.Bv + e * (n + 1);
+    const ConstF dAa = (ConstF)a.dlnA_da + e * (n + 1);
+    const ConstF dAb = (ConstF)a.dlnA_db + e * (n + 1);
+    const ConstF dAs = (ConstF)a.dlnA_ds + e * (n + 1);
+    const ConstF dBa = (ConstF)a.dB_da + e * (n + 1);
     const float fx = fxv[e];
     float Fb = 0.0f, Ae_sum = 0.0f;
     // x adjoint needs sum_c w^c A^{c,e}; A^{c,e} = F CW1 - acc - coupon terms
@@ -225,7 +230,7 @@ __device__ void pricing_adjoint(const AdjArgs& a, int i, int64_t kl, const float
       float zb = 0.0f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const float g = s.G[(c * NE + e) * P2 + kk];
+        const float g = G[(c * NE + e) * P2 + kk];
         acc[c] += zc * g;
         zb -= wc[c] * fx * g;                  // dJ/dZ_k
       }
@@ -239,10 +244,10 @@ __device__ void pricing_adjoint(const AdjArgs& a, int i, int64_t kl, const float
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int base = (c * NE + e) * P2;
-      float v = Fv[e] * s.CW1[base + pmin] - acc[c];
-      if (coupon) v -= s.CW2[base + pmin] + s.W1[base + pnow];
+      float v = Fv[e] * CW1[base + pmin] - acc[c];
+      if (coupon) v -= CW2[base + pmin] + W1[base + pnow];
       Ae_sum += wc[c] * v;
-      Fb += wc[c] * fx * s.CW1[base + pmin];
+      Fb += wc[c] * fx * CW1[base + pmin];
     }
     if (e > 0) ad.xb[e - 1] += fx * Ae_sum;   // d chi / d x = chi
     if (i > 0) {
