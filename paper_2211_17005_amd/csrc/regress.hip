@@ -735,14 +735,16 @@ struct Team {
 // ------------------------------------------------------------------------------------------
 struct AdamStep {
   float lr, b1, b2, eps, ic1, ic2;      // ic1 = 1 / (1 - b1^t), ic2 = 1 / (1 - b2^t)
+  // The fused multiply-adds are written out: left to contraction, which products fuse would
+  // depend on the code around each call site, and so would the rounding of the step.
   __device__ float operator()(float p, float g, float* m, float* v) const {
-    const float mm = b1 * *m + (1.0f - b1) * g;
-    const float vv = b2 * *v + (1.0f - b2) * g * g;
+    const float mm = __builtin_fmaf(1.0f - b1, g, b1 * *m);
+    const float vv = __builtin_fmaf((1.0f - b2) * g, g, b2 * *v);
     *m = mm;
     *v = vv;
     // hardware square root and reciprocal (about 1 ulp): the step size needs no more
     const float den = __builtin_amdgcn_sqrtf(vv * ic2) + eps;
-    return p - lr * (mm * ic1) * __builtin_amdgcn_rcpf(den);
+    return __builtin_fmaf(-(lr * (mm * ic1)), __builtin_amdgcn_rcpf(den), p);
   }
 };
 
@@ -867,16 +869,22 @@ __device__ void team_step(const Smem<U, H>& S, const MlpArgs& a, Team& tm, int t
   constexpr int kAdamBatch = 8;
   for (int p0 = lo + opaque_tid(); p0 < hi; p0 += kMlpThreads * kAdamBatch) {
     float g[kAdamBatch], pv[kAdamBatch], mv[kAdamBatch], vv[kAdamBatch];
+    // a batch member past the slice reads the slice's last element (in bounds, never stored): the
+    // loads carry no branch, so the batch's state loads are all in flight together, and each
+    // member's kAdamBatch gradient loads after them (the sum over members keeps its order)
+    int qc[kAdamBatch];
 #pragma unroll
     for (int u = 0; u < kAdamBatch; ++u) {
-      const int q = p0 + u * kMlpThreads;
-      g[u] = pv[u] = mv[u] = vv[u] = 0.0f;
-      if (q < hi) {
-        for (int j = 0; j < tm.G; ++j) g[u] += part0[(int64_t)j * NP + q];
-        pv[u] = Pr[q];
-        mv[u] = Mr[q];
-        vv[u] = Vr[q];
-      }
+      qc[u] = min(p0 + u * kMlpThreads, hi - 1);
+      g[u] = 0.0f;
+      pv[u] = Pr[qc[u]];
+      mv[u] = Mr[qc[u]];
+      vv[u] = Vr[qc[u]];
+    }
+    for (int j = 0; j < tm.G; ++j) {
+      const float* __restrict__ pj = part0 + (int64_t)j * NP;
+#pragma unroll
+      for (int u = 0; u < kAdamBatch; ++u) g[u] += pj[qc[u]];
     }
 #pragma unroll
     for (int u = 0; u < kAdamBatch; ++u) {
