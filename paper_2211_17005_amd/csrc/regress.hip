@@ -859,8 +859,8 @@ __device__ void team_step(const Smem<U, H>& S, const MlpArgs& a, Team& tm, int t
     S.scal()[3] = 0.0f;
   }
   tm.sync();
-  // this member's slice of the parameters: the loads of kAdamBatch elements per thread are issued
-  // before any of them is used (restrict views: the stores of a batch do not alias the next loads)
+  // this member's slice of the parameters, kAdamBatch elements per thread at a time (restrict
+  // views: the stores of a batch do not alias the next batch's loads)
   const float* __restrict__ part0 = a.partial + (int64_t)team * tm.G * NP;
   float* __restrict__ Pr = P;
   float* __restrict__ Mr = Mm;
@@ -868,23 +868,34 @@ __device__ void team_step(const Smem<U, H>& S, const MlpArgs& a, Team& tm, int t
   const int lo = (int)((int64_t)NP * tm.member / tm.G), hi = (int)((int64_t)NP * (tm.member + 1) / tm.G);
   constexpr int kAdamBatch = 8;
   for (int p0 = lo + opaque_tid(); p0 < hi; p0 += kMlpThreads * kAdamBatch) {
+    // a batch element past the slice reads the slice's last parameter (in bounds, never stored),
+    // so no load is predicated; the members' gradients are summed first (in member order), then
+    // the batch's Adam state is loaded
     float g[kAdamBatch], pv[kAdamBatch], mv[kAdamBatch], vv[kAdamBatch];
-    // a batch member past the slice reads the slice's last element (in bounds, never stored): the
-    // loads carry no branch, so the batch's state loads are all in flight together, and each
-    // member's kAdamBatch gradient loads after them (the sum over members keeps its order)
     int qc[kAdamBatch];
 #pragma unroll
     for (int u = 0; u < kAdamBatch; ++u) {
       qc[u] = min(p0 + u * kMlpThreads, hi - 1);
       g[u] = 0.0f;
-      pv[u] = Pr[qc[u]];
-      mv[u] = Mr[qc[u]];
-      vv[u] = Vr[qc[u]];
     }
     for (int j = 0; j < tm.G; ++j) {
       const float* __restrict__ pj = part0 + (int64_t)j * NP;
+      float t[kAdamBatch];
 #pragma unroll
-      for (int u = 0; u < kAdamBatch; ++u) g[u] += pj[qc[u]];
+      for (int u = 0; u < kAdamBatch; ++u) t[u] = pj[qc[u]];
+      // all of a member's loads are issued before the first add (left alone, the register
+      // allocator gives them one register and waits for each load in turn)
+      static_assert(kAdamBatch == 8, "one operand per batch element");
+      asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]),
+                   "+v"(t[7]));
+#pragma unroll
+      for (int u = 0; u < kAdamBatch; ++u) g[u] += t[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kAdamBatch; ++u) {
+      pv[u] = Pr[qc[u]];
+      mv[u] = Mr[qc[u]];
+      vv[u] = Vr[qc[u]];
     }
 #pragma unroll
     for (int u = 0; u < kAdamBatch; ++u) {
