@@ -636,45 +636,82 @@ __device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, const Masks
   }
 }
 
-// Gradients of one chunk, accumulated over the batch.  dff of the chunk's rows is in LDS.
+// Output unit of one chunk after its forward pass, and dZ_H = [A_H > 0] dff w_out^T in place.
+// The waves derive dff of their own rows from the out-block partials (the same sum in the same
+// order as a single wave would, so no phase of one wave precedes the others), keep the
+// partial sums of dff^T A_H (output weights) per wave in the reduction area, and leave each row's
+// loss and output gradients in dpred / dff for their fixed-order sums after the barrier.  ybuf / wbuf still hold this chunk's rows: the next chunk is staged
+// after the barrier.
 template <int U, int H>
-__device__ void backward(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW, const __bf16* a0) {
+__device__ void backward_output(const Smem<U, H>& S, int n, float inv_batch, int pos) {
   const int tid = opaque_tid();
-  // dZ_H = [A_H > 0] dff w_out^T in place, and the partial sums of dff^T A_H (output weights)
+  constexpr int UQ = U / 4, RS = kMlpThreads / UQ, RPS = kMlpRows / RS;
+  const int uq = tid % UQ, rs = tid / UQ;
+  const f32x4 wo = *(const f32x4*)&S.wout()[4 * uq];
+  const float mu = S.scal()[1];
+  // lane uq of a row group derives row rs RPS + uq % RPS (each row once per RPS lanes); the
+  // group's lanes then take the values of their rows from the group's first RPS lanes
+  float dp, dmine;
   {
-    constexpr int UQ = U / 4, RS = kMlpThreads / UQ, RPS = kMlpRows / RS;
-    const int uq = tid % UQ, rs = tid / UQ;
-    const f32x4 wo = *(const f32x4*)&S.wout()[4 * uq];
-    f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int k = 0; k < RPS; ++k) {
-      const int r = rs * RPS + k;
-      bf16x4* p = (bf16x4*)&S.A(H)[lidx(r, 4 * uq, Smem<U, H>::SW)];
-      const bf16x4 a = *p;
-      const float d = S.dff()[r];
-      bf16x4 z;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float av = (float)a[q];
-        z[q] = av > 0.0f ? (__bf16)(d * wo[q]) : (__bf16)0.0f;
-        g[q] += d * av;
-      }
-      *p = z;
+    const int r = rs * RPS + uq % RPS;
+    const float f = output_of_row<U, H>(S, r);
+    const float pred = (pos ? fmaxf(f, 0.0f) : f) + mu;
+    dp = r < n ? 2.0f * S.wbuf()[r] * (pred - S.ybuf()[r]) * inv_batch : 0.0f;
+    dmine = pos ? (f > 0.0f ? dp : 0.0f) : dp;
+    if (uq < RPS) {
+      S.dpred()[r] = dp;
+      S.dff()[r] = dmine;
     }
-    // lanes of a wave that share uq first (the reduction area holds one partial per wave)
-#pragma unroll
-    for (int m = UQ; m < 64; m <<= 1)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) g[q] += __shfl_xor(g[q], m);
-    if (lane_id() < UQ) ((f32x4*)S.red())[wave_id() * UQ + uq] = g;
   }
+  const int src0 = lane_id() - uq;
+  f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < RPS; ++k) {
+    const int r = rs * RPS + k;
+    const float d = __shfl(dmine, src0 + k);
+    bf16x4* p = (bf16x4*)&S.A(H)[lidx(r, 4 * uq, Smem<U, H>::SW)];
+    const bf16x4 a = *p;
+    bf16x4 z;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float av = (float)a[q];
+      z[q] = av > 0.0f ? (__bf16)(d * wo[q]) : (__bf16)0.0f;
+      g[q] += d * av;
+    }
+    *p = z;
+  }
+  // lanes of a wave that share uq first (the reduction area holds one partial per wave)
+#pragma unroll
+  for (int m = UQ; m < 64; m <<= 1)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g[q] += __shfl_xor(g[q], m);
+  if (lane_id() < UQ) ((f32x4*)S.red())[wave_id() * UQ + uq] = g;
   __syncthreads();
+}
+
+// Gradients of one chunk, accumulated over the batch (after backward_output): the output
+// weights' and the output bias / shift's chunk sums, then the hidden layers.
+template <int U, int H>
+__device__ void backward_layers(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW,
+                                const __bf16* a0) {
+  const int tid = opaque_tid();
   if (tid < U) {
     const float* part = (const float*)S.red();
     float s = S.gwout()[tid];
 #pragma unroll
     for (int w = 0; w < kMlpWaves; ++w) s += part[w * U + tid];
     S.gwout()[tid] = s;
+  }
+  // the chunk's sums of the loss gradient (output shift) and of dff (output bias), one row per
+  // lane, in a wave that has no output-weight sum to do
+  constexpr int kSumWave = U >= 64 ? U / 64 : 1;
+  if (wave_id() == kSumWave) {
+    const int r = lane_id();
+    const float gm = wave_sum(S.dpred()[r]), gb = wave_sum(S.dff()[r]);
+    if (r == 0) {
+      S.scal()[3] += gm;
+      S.scal()[2] += gb;
+    }
   }
   layer_backward<U, H, H>(S, ln, mk, accW, a0);
 }
@@ -1388,26 +1425,13 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
         const int n = rows(r0);
         const __bf16* a0 = S.in_buf(parity);
         const Masks mk = forward<U, H>(S, ln, a0);
-        if (opaque_tid() < R) {             // wave 0: one row per lane
-          const int r = opaque_tid();
-          const float f = output_of_row<U, H>(S, r);
-          const float pred = (pos ? fmaxf(f, 0.0f) : f) + S.scal()[1];
-          const float dp = r < n ? 2.0f * S.wbuf()[r] * (pred - S.ybuf()[r]) * inv_batch : 0.0f;
-          const float df = pos ? (f > 0.0f ? dp : 0.0f) : dp;
-          S.dff()[r] = df;
-          const float gm = wave_sum(dp), gb = wave_sum(df);
-          if (r == 0) {
-            S.scal()[3] += gm;
-            S.scal()[2] += gb;
-          }
-        }
-        __syncthreads();
+        backward_output<U, H>(S, n, inv_batch, pos);
         if (r0 + cstride < b1) {
           const int nn = rows(r0 + cstride);
           store_chunk<U, H>(S, c, feed.weight(S.wbase(), r0 + cstride, nn), nn, S.in_buf(parity ^ 1));
           if (r0 + 2 * cstride < b1) c = feed.load(r0 + 2 * cstride, rows(r0 + 2 * cstride));
         }
-        backward<U, H>(S, ln, mk, accW, a0);
+        backward_layers<U, H>(S, ln, mk, accW, a0);
         parity ^= 1;
       }
       p1 *= a.beta1;
