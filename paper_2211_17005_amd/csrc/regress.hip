@@ -266,6 +266,13 @@ struct DwMap {
   static constexpr int BO = TW / BI;
   static constexpr int NIB = KT / BI, NOB = NT / BO;
   static_assert(BO * BI == TW && NIB * NOB * TW == NT * KT && NIB * NOB <= kMlpWaves, "tiling");
+  // Block (in block fastest) of a wave.  The waves of a workgroup are placed on the four SIMDs in
+  // turn (wave w on SIMD w % 4), so waves w and w + 4 share a SIMD; they take neighbouring blocks,
+  // which puts the blocks of in block 0 (the bias tiles' extra products) on different SIMDs.
+  static __device__ __forceinline__ int block(int wave) { return (wave % 4) * 2 + wave / 4; }
+  static __device__ __forceinline__ int ib_of(int wave) { return block(wave) % NIB; }
+  static __device__ __forceinline__ int ob_of(int wave) { return block(wave) / NIB; }
+  static_assert(kMlpWaves == 8, "block(): two waves per SIMD");
 };
 
 // Weights of layer l from FP32 global memory into the BF16 LDS copy, two consecutive inputs of
@@ -531,7 +538,7 @@ template <int U, int H, int L>
 __device__ void accumulate_dw(const Smem<U, H>& S, const Lanes& ln, f32x4* accW, const __bf16* a0) {
   using M = DwMap<U, L>;
   const int wave = wave_id(), lane = lane_id();
-  const int ib = wave % M::NIB, ob = wave / M::NIB;
+  const int ib = M::ib_of(wave), ob = M::ob_of(wave);
   if (ob >= M::NOB) return;
   const __bf16* dZ = S.A(dz_buf(L, H));
   const __bf16* Ain = L == 1 ? a0 : S.A(L - 1);
@@ -694,24 +701,24 @@ __device__ void backward_output(const Smem<U, H>& S, int n, float inv_batch, int
 template <int U, int H>
 __device__ void backward_layers(const Smem<U, H>& S, const Lanes& ln, const Masks& mk, f32x4* accW,
                                 const __bf16* a0) {
-  const int tid = opaque_tid();
-  if (tid < U) {
+  // These sums go to the second wave of each SIMD (waves 4 .. 7), whose weight-gradient blocks
+  // carry no bias tiles when a layer has two or more in blocks: the output weights' chunk sums
+  // (one unit per thread), and the chunk's sums of the loss gradient (output shift) and of dff
+  // (output bias), one row per lane, in waves 6 and 7.
+  static_assert(U <= 2 * 64 && kMlpRows == 64, "waves 4 and 5 hold the output units");
+  const int u = opaque_tid() - 4 * 64;
+  if (u >= 0 && u < U) {
     const float* part = (const float*)S.red();
-    float s = S.gwout()[tid];
+    float s = S.gwout()[u];
 #pragma unroll
-    for (int w = 0; w < kMlpWaves; ++w) s += part[w * U + tid];
-    S.gwout()[tid] = s;
+    for (int w = 0; w < kMlpWaves; ++w) s += part[w * U + u];
+    S.gwout()[u] = s;
   }
-  // the chunk's sums of the loss gradient (output shift) and of dff (output bias), one row per
-  // lane, in a wave that has no output-weight sum to do
-  constexpr int kSumWave = U >= 64 ? U / 64 : 1;
-  if (wave_id() == kSumWave) {
+  const int wave = wave_id();
+  if (wave >= 6) {
     const int r = lane_id();
-    const float gm = wave_sum(S.dpred()[r]), gb = wave_sum(S.dff()[r]);
-    if (r == 0) {
-      S.scal()[3] += gm;
-      S.scal()[2] += gb;
-    }
+    const float t = wave_sum(wave == 6 ? S.dpred()[r] : S.dff()[r]);
+    if (r == 0) S.scal()[wave == 6 ? 3 : 2] += t;
   }
   layer_backward<U, H, H>(S, ln, mk, accW, a0);
 }
@@ -791,7 +798,7 @@ __device__ void adam_layer(const Smem<U, H>& S, const MlpLayout& Lay, float* P, 
   using M = DwMap<U, L>;
   constexpr int K = L == 1 ? kMlpDin : U, SWl = Smem<U, H>::lds(L);
   const int wave = wave_id(), lane = lane_id();
-  const int ib = wave % M::NIB, ob = wave / M::NIB;
+  const int ib = M::ib_of(wave), ob = M::ob_of(wave);
   if (ob >= M::NOB) return;
   f32x4* acc = accW + dw_base(U, L);
 #pragma unroll
@@ -857,7 +864,7 @@ __device__ void publish_dw(const MlpLayout& Lay, float* part, f32x4* accW) {
   using M = DwMap<U, L>;
   constexpr int K = L == 1 ? kMlpDin : U;
   const int wave = wave_id(), lane = lane_id();
-  const int ib = wave % M::NIB, ob = wave / M::NIB;
+  const int ib = M::ib_of(wave), ob = M::ob_of(wave);
   if (ob >= M::NOB) return;
   f32x4* acc = accW + dw_base(U, L);
 #pragma unroll
