@@ -246,6 +246,7 @@ struct Blk {
   static constexpr int BR = kTile == 0 ? (U >= 128 ? 2 : 1) : kTile == 1 ? 1 : (U >= 128 ? 4 : U >= 64 ? 2 : 1);
   static constexpr int NOB = NT / BO;
   static_assert(NOB * (RT / BR) == kMlpWaves, "one block per wave");
+  static_assert(BO * BR <= 8, "a lane's ReLU mask bits of a layer fit in one word");
 };
 
 // Weight-gradient tiles of layer L (U/16 out tiles by K_L/16 in tiles), held in registers over a
@@ -392,25 +393,49 @@ __device__ __forceinline__ RowTarget store_chunk(const Smem<U, H>& S, const Chun
 // ------------------------------------------------------------------------------------------
 // forward
 // ------------------------------------------------------------------------------------------
-// ReLU of rounded values on the packed 16-bit words: a BF16 word is below zero exactly when its
-// sign bit is set, i.e. when it is negative as a 16-bit integer, so max(word, 0) over integers is
-// the ReLU (rounding to nearest commutes with it; -0 becomes +0).
-typedef short s16x4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ bf16x4 relu_bf16(const bf16x4& h) {
-  return __builtin_bit_cast(bf16x4, __builtin_elementwise_max(__builtin_bit_cast(s16x4, h), (s16x4)0));
+// Packed BF16 pairs: element 0 in the low half of a 32-bit word, element 1 in the high half.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// (lo, hi) rounded to BF16 (nearest even) in one word: one v_cvt_pk_bf16_f32.  The empty asm
+// hands the word on as it is: followed by 16-bit integer arithmetic, the pair would otherwise be
+// converted element by element and repacked.
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
+  asm("" : "+v"(w));
+  return w;
 }
 
-// Bit v set where h[v] != 0 (for h >= 0: where h[v] > 0), tested on the packed 16-bit words.
-__device__ __forceinline__ uint32_t nonzero_bits(const bf16x4& h) {
-  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-  const u32x2 w = __builtin_bit_cast(u32x2, h);
-  return (uint32_t)((w.x & 0xFFFFu) != 0u) | ((uint32_t)((w.x >> 16) != 0u) << 1) |
-         ((uint32_t)((w.y & 0xFFFFu) != 0u) << 2) | ((uint32_t)((w.y >> 16) != 0u) << 3);
+// ReLU of a rounded pair: a BF16 value is below zero exactly when its sign bit is set, i.e. when
+// it is negative as a 16-bit integer, so max(half, 0) over integers is the ReLU (rounding to
+// nearest commutes with it; -0 becomes +0).
+__device__ __forceinline__ uint32_t relu_pair(uint32_t w) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, w), (s16x2)0));
+}
+
+// 1 in each half of w that is not zero (for a ReLU output: that is positive), else 0: one
+// v_pk_min_u16 with (1, 1).  Written as an instruction: the compiler rewrites min(h, 1) as a
+// comparison per half, which costs a compare, a select and a repack per half.
+__device__ __forceinline__ uint32_t nonzero_halves(uint32_t w) {
+  uint32_t r;
+  asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(w), "s"(0x00010001u));
+  return r;
+}
+
+// 0xFFFF in each half of the word where bit k of that half of m is set, else 0 (k < 16; a
+// constant once the caller's loops are unrolled).
+__device__ __forceinline__ uint32_t expand_bit(uint32_t m, int k) {
+  const u16x2 up = __builtin_bit_cast(u16x2, m) << (u16x2)(unsigned short)(15 - k);
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(s16x2, up) >> (s16x2)15);
 }
 
 // Hidden layer L: A_L = relu(W_L A_{L-1} + b_L), BF16 into A(L).  Returns the lane's ReLU mask:
-// bit 4 (x BR + y) + v set when element v of its tile strip (x, y) is positive; the backward
-// pass produces dH_L in the same lanes and tile order, so the mask never goes through LDS.
+// for tile strip s = x BR + y (elements v = 0..3, packed in the words (v0, v1) and (v2, v3)),
+// bits 2 s and 2 s + 1 hold "v0 > 0" and "v2 > 0", bits 16 + 2 s and 17 + 2 s "v1 > 0" and
+// "v3 > 0" (each word's halves in the matching halves of the mask); the backward pass produces
+// dH_L in the same lanes and tile order, so the mask never goes through LDS.
 //
 // a0 is the input buffer of layer 1; with kKeep false the last layer does not store A_H (only the
 // output partials) and leaves its closing barrier to the caller (the scans stage the next
@@ -460,14 +485,14 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __
     if constexpr (L == H) wo = *(const f32x4*)&S.wout()[out0];
 #pragma unroll
     for (int y = 0; y < B::BR; ++y) {
-      bf16x4 h;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) h[v] = (__bf16)acc[x][y][v];
-      h = relu_bf16(h);
+      typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+      const uint32_t w0 = relu_pair(pack_bf16(acc[x][y][0], acc[x][y][1]));
+      const uint32_t w1 = relu_pair(pack_bf16(acc[x][y][2], acc[x][y][3]));
+      const bf16x4 h = __builtin_bit_cast(bf16x4, (u32x2){w0, w1});
       if constexpr (L == H)
 #pragma unroll
         for (int v = 0; v < 4; ++v) pf[y] += (float)h[v] * wo[v];
-      mask |= nonzero_bits(h) << (4 * (x * B::BR + y));
+      if constexpr (L < H) mask |= (nonzero_halves(w0) | (nonzero_halves(w1) << 1)) << (2 * (x * B::BR + y));
       if (kKeep || L < H) *tile_strip(Aout, oo, SW, rb * B::BR + y, ob * B::BO + x) = h;
     }
   }
@@ -619,11 +644,11 @@ __device__ void backprop_store(const Smem<U, H>& S, const Lanes& ln, const f32x4
   for (int x = 0; x < B::BO; ++x)
 #pragma unroll
     for (int y = 0; y < B::BR; ++y) {
-      bf16x4 z;
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        z[v] = (mask >> (4 * (x * B::BR + y) + v)) & 1u ? (__bf16)dh[x][y][v] : (__bf16)0.0f;
-      *tile_strip(dst, o, SW, rb * B::BR + y, ob * B::BO + x) = z;
+      typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+      const int k = 2 * (x * B::BR + y);
+      const uint32_t z0 = pack_bf16(dh[x][y][0], dh[x][y][1]) & expand_bit(mask, k);
+      const uint32_t z1 = pack_bf16(dh[x][y][2], dh[x][y][3]) & expand_bit(mask, k + 1);
+      *tile_strip(dst, o, SW, rb * B::BR + y, ob * B::BO + x) = __builtin_bit_cast(bf16x4, (u32x2){z0, z1});
     }
 }
 
@@ -676,16 +701,18 @@ __device__ void backward_output(const Smem<U, H>& S, int n, float inv_batch, int
   for (int k = 0; k < RPS; ++k) {
     const int r = rs * RPS + k;
     const float d = __shfl(dmine, src0 + k);
-    bf16x4* p = (bf16x4*)&S.A(H)[lidx(r, 4 * uq, Smem<U, H>::SW)];
-    const bf16x4 a = *p;
-    bf16x4 z;
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    u32x2* p = (u32x2*)&S.A(H)[lidx(r, 4 * uq, Smem<U, H>::SW)];
+    const u32x2 aw = *p;
+    const bf16x4 a = __builtin_bit_cast(bf16x4, aw);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float av = (float)a[q];
-      z[q] = av > 0.0f ? (__bf16)(d * wo[q]) : (__bf16)0.0f;
-      g[q] += d * av;
-    }
-    *p = z;
+    for (int q = 0; q < 4; ++q) g[q] += d * (float)a[q];
+    // z = d w_out where A_H > 0 (A_H holds no negative word), else +0: the halves' nonzero flags
+    // (0 or 1) negated are the word masks
+    const u16x2 zero = {0, 0};
+    const uint32_t m0 = __builtin_bit_cast(uint32_t, zero - __builtin_bit_cast(u16x2, nonzero_halves(aw.x)));
+    const uint32_t m1 = __builtin_bit_cast(uint32_t, zero - __builtin_bit_cast(u16x2, nonzero_halves(aw.y)));
+    *p = (u32x2){pack_bf16(d * wo[0], d * wo[1]) & m0, pack_bf16(d * wo[2], d * wo[3]) & m1};
   }
   // lanes of a wave that share uq first (the reduction area holds one partial per wave)
 #pragma unroll
