@@ -677,30 +677,40 @@ __device__ void layer_backward(const Smem<U, H>& S, const Lanes& ln, const Masks
 template <int U, int H>
 __device__ void backward_output(const Smem<U, H>& S, int n, float inv_batch, int pos) {
   const int tid = opaque_tid();
-  constexpr int UQ = U / 4, RS = kMlpThreads / UQ, RPS = kMlpRows / RS;
-  const int uq = tid % UQ, rs = tid / UQ;
+  constexpr int UQ = U / 4, RS = kMlpThreads / UQ, RPS = kMlpRows / RS, NG = 64 / UQ;
+  const int uq = (int)((unsigned)tid % UQ), rs = (int)((unsigned)tid / UQ);
   const f32x4 wo = *(const f32x4*)&S.wout()[4 * uq];
   const float mu = S.scal()[1];
-  // lane uq of a row group derives row rs RPS + uq % RPS (each row once per RPS lanes); the
-  // group's lanes then take the values of their rows from the group's first RPS lanes
+  // lane uq of a row group (UQ lanes, NG groups per wave) derives row rs RPS + uq % RPS (each row
+  // once per RPS lanes), its inputs read without a branch; the group's lanes then take the
+  // values of their rows from the group's first RPS lanes
   float dp, dmine;
   {
-    const int r = rs * RPS + uq % RPS;
+    const int r = rs * RPS + (int)((unsigned)uq % RPS);
+    const float w = S.wbuf()[r], y = S.ybuf()[r];
     const float f = output_of_row<U, H>(S, r);
     const float pred = (pos ? fmaxf(f, 0.0f) : f) + mu;
-    dp = r < n ? 2.0f * S.wbuf()[r] * (pred - S.ybuf()[r]) * inv_batch : 0.0f;
+    dp = r < n ? 2.0f * w * (pred - y) * inv_batch : 0.0f;
     dmine = pos ? (f > 0.0f ? dp : 0.0f) : dp;
     if (uq < RPS) {
       S.dpred()[r] = dp;
       S.dff()[r] = dmine;
     }
   }
-  const int src0 = lane_id() - uq;
   f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int k = 0; k < RPS; ++k) {
     const int r = rs * RPS + k;
-    const float d = __shfl(dmine, src0 + k);
+    // d of row r: lane k of this lane's row group (v_readlane of each group, then a select)
+    float d = dmine;
+    if constexpr (RPS > 1) {
+      d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dmine), k));
+#pragma unroll
+      for (int gi = 1; gi < NG; ++gi) {
+        const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dmine), gi * UQ + k));
+        d = lane_id() >= gi * UQ ? v : d;
+      }
+    }
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     u32x2* p = (u32x2*)&S.A(H)[lidx(r, 4 * uq, Smem<U, H>::SW)];
     const u32x2 aw = *p;
