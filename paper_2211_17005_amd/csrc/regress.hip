@@ -121,6 +121,17 @@ __device__ __forceinline__ float wave_sum(float v) {
           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48)));
 }
 
+// v + (v of lane l ^ m) for m = 16 or 32, with the gfx950 lane swaps (across 16-lane rows, across
+// the wave's halves): a swap of v with itself leaves the partner lane's v in one of the results.
+template <int m>
+__device__ __forceinline__ float xor_sum(float v) {
+  static_assert(m == 16 || m == 32, "row or half-wave exchange");
+  const unsigned x = __float_as_uint(v);
+  const auto sw = m == 32 ? __builtin_amdgcn_permlane32_swap(x, x, false, false)
+                          : __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  return __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+}
+
 // MFMA operand whose eight k values run along a row: lane l receives
 // M[row0 + l % 16][col0 + 8 (l / 16) + t], t = 0..7 (one 16-byte read).
 __device__ __forceinline__ bf16x8 frag_rows(const __bf16* M, const LaneOffsets& o, int S, int row0, int col0) {
@@ -500,8 +511,8 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __
     // the four lane groups hold the same rows: fold them, then one partial per out block and row
 #pragma unroll
     for (int y = 0; y < B::BR; ++y) {
-      pf[y] += __shfl_xor(pf[y], 16);
-      pf[y] += __shfl_xor(pf[y], 32);
+      pf[y] = xor_sum<16>(pf[y]);
+      pf[y] = xor_sum<32>(pf[y]);
       if (lane < 16) S.fpart()[ob * kMlpRows + 16 * (rb * B::BR + y) + lane] = pf[y];
     }
   }
@@ -726,9 +737,11 @@ __device__ void backward_output(const Smem<U, H>& S, int n, float inv_batch, int
   }
   // lanes of a wave that share uq first (the reduction area holds one partial per wave)
 #pragma unroll
-  for (int m = UQ; m < 64; m <<= 1)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) g[q] += __shfl_xor(g[q], m);
+  for (int q = 0; q < 4; ++q) {
+    if constexpr (UQ <= 8) g[q] += __shfl_xor(g[q], 8);
+    if constexpr (UQ <= 16) g[q] = xor_sum<16>(g[q]);
+    g[q] = xor_sum<32>(g[q]);
+  }
   if (lane_id() < UQ) ((f32x4*)S.red())[wave_id() * UQ + uq] = g;
   __syncthreads();
 }
