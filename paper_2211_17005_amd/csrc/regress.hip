@@ -95,6 +95,11 @@ struct LaneOffsets {
 // hidden layers), built once and kept in registers through the training loops.
 struct Lanes {
   LaneOffsets o0, o;
+  // The same with the wave's own output block (forward and back-propagation products) folded in,
+  // so that those reads and stores are one instruction at an immediate offset: row reads of its
+  // out block of W (strides S0, S), of its row block of the layer input or dZ (S0, S), its tile
+  // strips (S), and the transpose loads of its out block of W in the back-propagation (S).
+  int rows_ob0, rows_ob, rows_rb0, rows_rb, tile_w, bp_lo, bp_hi;
   __device__ __forceinline__ Lanes(int S0, int S) : o0(S0), o(S) {}
   __device__ __forceinline__ const LaneOffsets& of(int S, int S0) const { return S == S0 ? o0 : o; }
 };
@@ -132,12 +137,6 @@ __device__ __forceinline__ float xor_sum(float v) {
   return __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
 }
 
-// MFMA operand whose eight k values run along a row: lane l receives
-// M[row0 + l % 16][col0 + 8 (l / 16) + t], t = 0..7 (one 16-byte read).
-__device__ __forceinline__ bf16x8 frag_rows(const __bf16* M, const LaneOffsets& o, int S, int row0, int col0) {
-  return *(const bf16x8*)&M[o.rows + row0 * S + col0];
-}
-
 // MFMA operand whose eight k values run down a column: lane l receives
 // M[row0 + 8 (l / 16) + t][col0 + l % 16], t = 0..7 (two transpose loads of four rows each).
 __device__ __forceinline__ bf16x8 frag_cols(const __bf16* M, const LaneOffsets& o, int S, int row0, int col0) {
@@ -146,11 +145,6 @@ __device__ __forceinline__ bf16x8 frag_cols(const __bf16* M, const LaneOffsets& 
   return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// The 4 x 1 strip of a 16 x 16 MFMA result tile held by a lane: rows 16 rt + l % 16,
-// columns 16 ot + 4 (l / 16) .. + 3 (four consecutive elements, one 8-byte access).
-__device__ __forceinline__ bf16x4* tile_strip(__bf16* M, const LaneOffsets& o, int S, int rt, int ot) {
-  return (bf16x4*)&M[o.tile + 16 * rt * S + 16 * ot];
-}
 
 // ------------------------------------------------------------------------------------------
 // per-date input scaling (population mean / std of each feature, RMS of the target)
@@ -259,6 +253,24 @@ struct Blk {
   static_assert(NOB * (RT / BR) == kMlpWaves, "one block per wave");
   static_assert(BO * BR <= 8, "a lane's ReLU mask bits of a layer fit in one word");
 };
+
+// A thread's lane offsets with its wave's output block of the forward and back-propagation
+// products (built once per fit).
+template <int U, int H>
+__device__ __forceinline__ Lanes make_lanes() {
+  using B = Blk<U>;
+  constexpr int S0 = Smem<U, H>::SW0, S = Smem<U, H>::SW;
+  Lanes ln(S0, S);
+  const int wave = wave_id(), ob = wave % B::NOB, rb = wave / B::NOB;
+  ln.rows_ob0 = ln.o0.rows + 16 * ob * B::BO * S0;
+  ln.rows_ob = ln.o.rows + 16 * ob * B::BO * S;
+  ln.rows_rb0 = ln.o0.rows + 16 * rb * B::BR * S0;
+  ln.rows_rb = ln.o.rows + 16 * rb * B::BR * S;
+  ln.tile_w = ln.o.tile + 16 * rb * B::BR * S + 16 * ob * B::BO;
+  ln.bp_lo = ln.o.cols_lo + 16 * ob * B::BO;
+  ln.bp_hi = ln.o.cols_hi + 16 * ob * B::BO;
+  return ln;
+}
 
 // Weight-gradient tiles of layer L (U/16 out tiles by K_L/16 in tiles), held in registers over a
 // batch: each wave owns a block of BO x BI of them (in block fastest); with fewer tiles than
@@ -458,8 +470,7 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __
   constexpr int SW = Smem<U, H>::SW;
   const int wave = wave_id(), lane = lane_id();
   const int ob = wave % B::NOB, rb = wave / B::NOB;
-  const LaneOffsets& oi = L == 1 ? ln.o0 : ln.o;
-  const LaneOffsets& oo = ln.o;
+  const int w_rows = L == 1 ? ln.rows_ob0 : ln.rows_ob, in_rows = L == 1 ? ln.rows_rb0 : ln.rows_rb;
   const __bf16* W = S.W(L);
   const __bf16* Ain = L == 1 ? a0 : S.A(L - 1);
   __bf16* Aout = S.A(L);
@@ -477,9 +488,9 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __
   for (int k0 = 0; k0 < K; k0 += 32) {
     bf16x8 av[B::BO], bv[B::BR];
 #pragma unroll
-    for (int x = 0; x < B::BO; ++x) av[x] = frag_rows(W, oi, SWl, 16 * (ob * B::BO + x), k0);
+    for (int x = 0; x < B::BO; ++x) av[x] = *(const bf16x8*)&W[w_rows + 16 * x * SWl + k0];
 #pragma unroll
-    for (int y = 0; y < B::BR; ++y) bv[y] = frag_rows(Ain, oi, SWl, 16 * (rb * B::BR + y), k0);
+    for (int y = 0; y < B::BR; ++y) bv[y] = *(const bf16x8*)&Ain[in_rows + 16 * y * SWl + k0];
 #pragma unroll
     for (int x = 0; x < B::BO; ++x)
 #pragma unroll
@@ -504,7 +515,7 @@ __device__ uint32_t forward_layer(const Smem<U, H>& S, const Lanes& ln, const __
 #pragma unroll
         for (int v = 0; v < 4; ++v) pf[y] += (float)h[v] * wo[v];
       if constexpr (L < H) mask |= (nonzero_halves(w0) | (nonzero_halves(w1) << 1)) << (2 * (x * B::BR + y));
-      if (kKeep || L < H) *tile_strip(Aout, oo, SW, rb * B::BR + y, ob * B::BO + x) = h;
+      if (kKeep || L < H) *(bf16x4*)&Aout[ln.tile_w + 16 * y * SW + 16 * x] = h;
     }
   }
   if constexpr (L == H) {
@@ -617,9 +628,6 @@ template <int U, int H, int L>
 __device__ void backprop_compute(const Smem<U, H>& S, const Lanes& ln, f32x4 (&dh)[Blk<U>::BO][Blk<U>::BR]) {
   using B = Blk<U>;
   constexpr int SW = Smem<U, H>::SW;
-  const int wave = wave_id();
-  const int ob = wave % B::NOB, rb = wave / B::NOB;
-  const LaneOffsets& o = ln.o;
   const __bf16* W = S.W(L);
   const __bf16* dZ = S.A(dz_buf(L, H));
 #pragma unroll
@@ -630,9 +638,13 @@ __device__ void backprop_compute(const Smem<U, H>& S, const Lanes& ln, f32x4 (&d
   for (int k0 = 0; k0 < U; k0 += 32) {
     bf16x8 av[B::BO], bv[B::BR];
 #pragma unroll
-    for (int x = 0; x < B::BO; ++x) av[x] = frag_cols(W, o, SW, k0, 16 * (ob * B::BO + x));
+    for (int x = 0; x < B::BO; ++x) {
+      const bf16x4 lo = lds_read_tr(W + ln.bp_lo + k0 * SW + 16 * x);
+      const bf16x4 hi = lds_read_tr(W + ln.bp_hi + k0 * SW + 16 * x);
+      av[x] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
 #pragma unroll
-    for (int y = 0; y < B::BR; ++y) bv[y] = frag_rows(dZ, o, SW, 16 * (rb * B::BR + y), k0);
+    for (int y = 0; y < B::BR; ++y) bv[y] = *(const bf16x8*)&dZ[ln.rows_rb + 16 * y * SW + k0];
 #pragma unroll
     for (int x = 0; x < B::BO; ++x)
 #pragma unroll
@@ -647,9 +659,6 @@ __device__ void backprop_store(const Smem<U, H>& S, const Lanes& ln, const f32x4
                                uint32_t mask) {
   using B = Blk<U>;
   constexpr int SW = Smem<U, H>::SW;
-  const int wave = wave_id();
-  const int ob = wave % B::NOB, rb = wave / B::NOB;
-  const LaneOffsets& o = ln.o;
   __bf16* dst = S.A(dz_buf(L - 1, H));
 #pragma unroll
   for (int x = 0; x < B::BO; ++x)
@@ -659,7 +668,7 @@ __device__ void backprop_store(const Smem<U, H>& S, const Lanes& ln, const f32x4
       const int k = 2 * (x * B::BR + y);
       const uint32_t z0 = pack_bf16(dh[x][y][0], dh[x][y][1]) & expand_bit(mask, k);
       const uint32_t z1 = pack_bf16(dh[x][y][2], dh[x][y][3]) & expand_bit(mask, k + 1);
-      *tile_strip(dst, o, SW, rb * B::BR + y, ob * B::BO + x) = __builtin_bit_cast(bf16x4, (u32x2){z0, z1});
+      *(bf16x4*)&dst[ln.tile_w + 16 * y * SW + 16 * x] = __builtin_bit_cast(bf16x4, (u32x2){z0, z1});
     }
 }
 
@@ -1311,7 +1320,7 @@ __device__ void loss_helper(const Smem<U, H>& S, const MlpArgs& a) {
   int& s_q = ((int*)S.dpred())[0];
   int& s_state = ((int*)S.dpred())[1];
   int& s_best = ((int*)S.dpred())[2];
-  const Lanes ln(Smem<U, H>::SW0, Smem<U, H>::SW);
+  const Lanes ln = make_lanes<U, H>();
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_q = __hip_atomic_fetch_add(a.lqueue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1456,7 +1465,7 @@ __device__ void train_one(const Smem<U, H>& S, const MlpArgs& a, int job, Team& 
   }
   __syncthreads();
 
-  const Lanes ln(Smem<U, H>::SW0, Smem<U, H>::SW);
+  const Lanes ln = make_lanes<U, H>();
   const Feeder feed(a, date);
   float best = INFINITY;
   int pos = 0;
@@ -1571,7 +1580,7 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_predict_kernel(const MlpArgs 
   load_weights<U, H>(S, rec, L);
   __syncthreads();
   const float ysc = rec[L.yscale_off()];
-  const Lanes ln(Smem<U, H>::SW0, Smem<U, H>::SW);
+  const Lanes ln = make_lanes<U, H>();
   const Feeder feed(a, date);
   auto rows = [&](int64_t r0) { return (int)max((int64_t)0, min((int64_t)R, k1 - r0)); };
   ChunkRegs c = feed.load(k0, rows(k0));
