@@ -1133,12 +1133,20 @@ __device__ void refit(const Smem<U, H>& S, const Lanes& ln, const Feeder& feed, 
     }
     {
       const int u = tid % U, grp = tid / U;
-#pragma unroll 1
-      for (int r = grp; r < n; r += NGRP) {
-        // with weights the stored row is sqrt(w) h: one more sqrt(w) gives w h
+      // with weights the stored row is sqrt(w) h: one more sqrt(w) gives w h
+      auto column_row = [&](int r) {
         const double h = (double)(float)Hh[lidx(r, u, Smem<U, H>::SW)] * (weighted ? sqrt((double)S.wbuf()[r]) : 1.0);
         hs += h;
         hy += h * (double)(S.ybuf()[r] - mu);
+      };
+      if (n == R && !weighted) {
+        // a full chunk: the thread's rows unrolled, so that their LDS reads are issued together
+        // (the sums keep the row order)
+#pragma unroll
+        for (int r = grp; r < R; r += NGRP) column_row(r);
+      } else {
+#pragma unroll 1
+        for (int r = grp; r < n; r += NGRP) column_row(r);
       }
       if (u == 0)
         for (int r = grp; r < n; r += NGRP) {
